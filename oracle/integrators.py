@@ -1,0 +1,64 @@
+"""Fine and coarse propagators (test infrastructure only).
+
+Sec. 1 states that any explicit time marching scheme (forward Euler, Runge-Kutta)
+applied to the matrix ODE approximates f(A); Alg. 1 (Sec. 2) needs a cheap
+coarse propagator G(T_{n+1}, T_n, x) and an accurate fine propagator
+F(T_{n+1}, T_n, x), both mapping a value at T_n to one at T_{n+1}.
+
+* Fine F: `steps` classical four-stage Runge-Kutta steps of size
+  h = (T_{n+1} - T_n) / steps:
+      k1 = F(X), k2 = F(X + h/2 k1), k3 = F(X + h/2 k2), k4 = F(X + h k3),
+      X <- X + h/6 (k1 + 2 k2 + 2 k3 + k4).
+* Coarse G: `steps` forward-Euler steps X <- X + h F(X).
+
+The flows are autonomous, so only the step size depends on the times.
+
+Parity: pinned by convergence order (RK4 error ratio 16, Euler ratio 2 when h
+halves) against the closed forms in ``exact`` (tests/test_oracle_flows.py).
+"""
+
+from .flows import rhs, shifted
+from .core import HOMOTOPY
+
+
+def rk4_step(alg, kind, X, A, h, M=None):
+    if kind == HOMOTOPY and M is None:
+        M = shifted(alg, A)
+    k1 = rhs(alg, kind, X, A, M)
+    k2 = rhs(alg, kind, X + (h / 2) * k1, A, M)
+    k3 = rhs(alg, kind, X + (h / 2) * k2, A, M)
+    k4 = rhs(alg, kind, X + h * k3, A, M)
+    return X + (h / 6) * (k1 + 2 * k2 + 2 * k3 + k4)
+
+
+def euler_step(alg, kind, X, A, h, M=None):
+    return X + h * rhs(alg, kind, X, A, M)
+
+
+def fine(alg, kind, A, X, t_next, t_cur, steps):
+    """F(t_next, t_cur, X): `steps` RK4 steps from t_cur to t_next."""
+    h = (t_next - t_cur) / steps
+    M = shifted(alg, A) if kind == HOMOTOPY else None
+    for _ in range(steps):
+        X = rk4_step(alg, kind, X, A, h, M)
+    return X
+
+
+def coarse(alg, kind, A, X, t_next, t_cur, steps=1):
+    """G(t_next, t_cur, X): `steps` forward-Euler steps from t_cur to t_next."""
+    h = (t_next - t_cur) / steps
+    M = shifted(alg, A) if kind == HOMOTOPY else None
+    for _ in range(steps):
+        X = euler_step(alg, kind, X, A, h, M)
+    return X
+
+
+def serial_fine(alg, kind, A, X0, T, N, steps):
+    """The fine propagator applied slice after slice: X_{n+1} = F(T_{n+1}, T_n, X_n).
+
+    Returns the list [X_0, ..., X_N] on the uniform grid T_n = n T / N.
+    """
+    out = [X0]
+    for n in range(N):
+        out.append(fine(alg, kind, A, out[-1], (n + 1) * T / N, n * T / N, steps))
+    return out
