@@ -1,0 +1,169 @@
+/*
+ * fm.h -- C interface of the MI355X (gfx950) parareal matrix-function library.
+ *
+ * The library evaluates f(A) for a dense real n x n matrix A as the value at
+ * time T of a matrix ODE (the homotopy model of Sec. 1 of Chehab & Petcu,
+ * "Parallel Matrix Function Evaluation via Initial value ODE modelling") or as
+ * the stable steady state of one (the steady-state model of Sec. 1 / Sec. 4),
+ * integrating the ODE with the classical parareal algorithm (Sec. 2, Alg. 1):
+ * a cheap coarse propagator G swept serially over N time slices, corrected by
+ * an accurate fine propagator F whose N slice solves are independent.
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are FP64, row-major.  Pointers marked "device" are HIP device
+ *    pointers of the device that was current at fm_flow_create; pointers
+ *    marked "host" are ordinary host memory.  Pointer arrays (const double*
+ *    const*) are host arrays of `batch` device pointers.
+ *  - Every call returns an fm_status; nothing throws across the interface.
+ *    On an error the thread-local message of fm_last_error() says why; no
+ *    output is written unless the status is FM_OK or FM_WARN_NOT_CONVERGED.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Calls order
+ *    their device work on it.  fm_parareal_solve synchronises with it (it reads
+ *    one scalar per iteration); the propagators are asynchronous.
+ *  - A flow object is not thread-safe: calls on one flow must not overlap.
+ */
+#ifndef FM_H
+#define FM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fm_flow_s* fm_flow;  /* opaque; owned by the library */
+
+typedef enum {
+  FM_OK = 0,
+  FM_WARN_NOT_CONVERGED = 1,  /* result written: the iterate after max_iter */
+  FM_ERR_INVALID = -1,        /* bad argument; nothing done */
+  FM_ERR_NOMEM = -2,          /* device allocation failed */
+  FM_ERR_DEVICE = -3,         /* HIP runtime error */
+  FM_ERR_NONFINITE = -4,      /* an iterate became Inf/NaN (e.g. A(t) singular) */
+  FM_ERR_UNSUPPORTED = -5     /* valid request this build does not implement */
+} fm_status;
+
+/* The matrix flows dX/dt = F(X). */
+typedef enum {
+  /* Sec. 2, Example 1: with A(t) = I + t (A - I), Q(t) = A(t)^{-1} solves
+   * dQ/dt = -Q (A - I) Q = Q (I - A) Q, Q(0) = I, Q(1) = A^{-1}.  Requires
+   * A(t) invertible on [0, 1] (e.g. A with positive eigenvalues); T = 1.     */
+  FM_FLOW_INV_HOMOTOPY = 1,
+  /* dX/dt = X - X A X: stable steady state A^{-1} (differential -Id there). */
+  FM_FLOW_INV_STEADY = 2,
+  /* dX/dt = A - X^2, A symmetric positive definite: stable steady state the
+   * principal square root A^{1/2}.                                           */
+  FM_FLOW_SQRT_STEADY = 3
+} fm_flow_kind;
+
+/* Arithmetic of the dense products of the propagators (MFMA input type).  The
+ * parareal iterates, the correction sum, the residual and the refinement are
+ * always FP64; with FM_F32/BF16/F16 products accumulate in FP32 and the
+ * propagator state is kept in FP64 between products. */
+typedef enum { FM_F64 = 0, FM_F32 = 1, FM_BF16 = 2, FM_F16 = 3 } fm_dtype;
+
+/* Coarse propagator G. */
+typedef enum {
+  FM_COARSE_EULER = 0,    /* forward Euler steps */
+  FM_COARSE_LEARNED = 1   /* degree-3 polynomial step X p(K) + q(K), K = h B X,
+                             coefficients from the loaded network, with a
+                             per-slice fallback to Euler (see fm_params)    */
+} fm_coarse;
+
+typedef struct {
+  int32_t kind;      /* fm_flow_kind */
+  int32_t reserved;  /* must be 0 */
+  int64_t n;         /* order, 1 <= n <= 16384 */
+  const double* A;   /* device, n x n, row-major, leading dimension lda; copied
+                        at fm_flow_create, may be freed afterwards        */
+  int64_t lda;       /* >= n */
+} fm_problem;
+
+/* Problem statement of Alg. 1 (Sec. 2): time interval [0, T] in N uniform
+ * slices T_n = n T / N; G = coarse_steps coarse steps per slice; F =
+ * fine_steps classical RK4 steps per slice.  Iteration k computes U^{k+1}
+ * from U^k; it stops after the first k with
+ *     max_n ||U^{k+1}_n - U^k_n||_F / ||U^{k+1}_n||_F <= tol,
+ * or after max_iter iterations, or at k + 1 = N (then U equals the serial fine
+ * solution).  After that, if max_refine > 0, FP64 refinement (Newton-Schulz
+ * for the inverse flows, Newton with a conjugate-gradient Sylvester solve for
+ * the square root) runs until the relative residual is <= refine_tol or
+ * max_refine steps were made. */
+typedef struct {
+  double T;              /* final time; FM_FLOW_INV_HOMOTOPY requires 1.0 */
+  int32_t N;             /* slices, 1..4096 */
+  int32_t coarse_steps;  /* >= 1 */
+  int32_t fine_steps;    /* >= 1 */
+  int32_t max_iter;      /* >= 0 (0: coarse sweep only) */
+  int32_t coarse;        /* fm_coarse */
+  int32_t max_refine;    /* >= 0 */
+  double tol;            /* >= 0 */
+  double refine_tol;     /* >= 0 */
+} fm_params;
+
+typedef struct {
+  int32_t iters;           /* parareal iterations performed */
+  int32_t refine_steps;    /* refinement updates performed */
+  int32_t learned_slices;  /* slice solves that used the learned step in the
+                              last iteration (0 for Euler)                  */
+  int32_t status;          /* fm_status of this instance */
+  double increment;        /* last increment (see fm_params) */
+  double residual_before;  /* FP64 relative residual before refinement:
+                              ||I - A X||_F / sqrt(n) or ||A - X^2||_F / ||A||_F */
+  double residual;         /* the same after refinement */
+  double hist[64];         /* increment of iterations 1..64 */
+} fm_stats;
+
+/*
+ * Create a flow object for `batch` problems (each its own A, n and kind) whose
+ * products run in `dtype`.  Stages A on the device (padded copy, A - I, the
+ * dtype copies); allocates the parareal workspace lazily in the first solve.
+ * options: NULL or "key=value;key=value": coarse_model=<path> loads learned
+ * coarse weights (file written by the training script), autotune=0|1 (default
+ * 1: time candidate tile shapes on first use), autotune_cache=<path>.
+ * out: host; receives the handle.  Returns FM_ERR_INVALID for batch < 1,
+ * n out of range, lda < n, an unknown kind/dtype or a NULL A.
+ */
+fm_status fm_flow_create(fm_flow* out, const fm_problem* problems, int32_t batch,
+                         int32_t dtype, const char* options, void* hip_stream);
+
+/*
+ * Run Alg. 1 on every problem of the flow and write f(A) (the last slice,
+ * after refinement) to X_out[b].  X0: host array of device pointers to the
+ * n x n initial values, or NULL for X0 = I (the choice of Sec. 2, Example 1).
+ * prm: host, `batch` entries (problem b uses prm[b]).  stats: host, `batch`
+ * entries, may be NULL.  Returns the worst status over the batch.
+ */
+fm_status fm_parareal_solve(fm_flow f, const double* const* X0, double* const* X_out,
+                            const fm_params* prm, fm_stats* stats, void* hip_stream);
+
+/*
+ * Fine propagator F(t_next, t_cur, X) of Alg. 1: `steps` classical RK4 steps of
+ * size (t_next - t_cur) / steps, for every problem b: X_out[b] = F(X_in[b]).
+ * X_in, X_out: host arrays of device pointers (n x n each); X_out[b] may
+ * equal X_in[b].
+ */
+fm_status fm_fine_propagate(fm_flow f, double t_next, double t_cur, int32_t steps,
+                            const double* const* X_in, double* const* X_out,
+                            void* hip_stream);
+
+/*
+ * Coarse propagator G(t_next, t_cur, X) of Alg. 1: `steps` forward-Euler steps
+ * (coarse = FM_COARSE_EULER) or learned polynomial steps (FM_COARSE_LEARNED,
+ * needs a loaded model; no fallback here), same layout as fm_fine_propagate.
+ */
+fm_status fm_coarse_propagate(fm_flow f, double t_next, double t_cur, int32_t steps,
+                              int32_t coarse, const double* const* X_in,
+                              double* const* X_out, void* hip_stream);
+
+/* Release the flow and all its device memory.  NULL is accepted. */
+void fm_destroy(fm_flow f);
+
+/* Thread-local message of the last error (empty string if none). */
+const char* fm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FM_H */

@@ -1,0 +1,162 @@
+// C interface of libfm (declared in include/fm.h): argument validation and
+// dispatch to the engine.  No exception crosses the interface.
+#include <cmath>
+#include <new>
+
+#include "engine.h"
+
+namespace fm {
+const char* last_error();
+}
+
+struct fm_flow_s {
+  fm::Flow impl;
+};
+
+using fm::set_error;
+
+static fm_status check_flow(fm_flow f) {
+  if (!f) {
+    set_error("flow handle is NULL");
+    return FM_ERR_INVALID;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != f->impl.device) {
+    set_error("flow was created on device %d but device %d is current", f->impl.device, dev);
+    return FM_ERR_INVALID;
+  }
+  return FM_OK;
+}
+
+static fm_status check_ptrs(const fm_flow f, const void* const* p, const char* name) {
+  if (!p) {
+    set_error("%s is NULL", name);
+    return FM_ERR_INVALID;
+  }
+  for (int i = 0; i < f->impl.batch; ++i)
+    if (!p[i]) {
+      set_error("%s[%d] is NULL", name, i);
+      return FM_ERR_INVALID;
+    }
+  return FM_OK;
+}
+
+extern "C" {
+
+fm_status fm_flow_create(fm_flow* out, const fm_problem* problems, int32_t batch, int32_t dtype,
+                         const char* options, void* hip_stream) {
+  fm::clear_error();
+  if (!out || !problems) {
+    set_error("out and problems must be non-NULL");
+    return FM_ERR_INVALID;
+  }
+  *out = nullptr;
+  if (batch < 1 || batch > (1 << 20)) {
+    set_error("batch %d out of range [1, 2^20]", batch);
+    return FM_ERR_INVALID;
+  }
+  if (dtype < FM_F64 || dtype > FM_F16) {
+    set_error("unknown dtype %d", dtype);
+    return FM_ERR_INVALID;
+  }
+  for (int i = 0; i < batch; ++i) {
+    const fm_problem& p = problems[i];
+    if (p.kind < FM_FLOW_INV_HOMOTOPY || p.kind > FM_FLOW_SQRT_STEADY) {
+      set_error("problem %d: unknown flow kind %d", i, p.kind);
+      return FM_ERR_INVALID;
+    }
+    if (p.n < 1 || p.n > 16384 || p.lda < p.n || !p.A || p.reserved != 0) {
+      set_error("problem %d: need 1 <= n <= 16384, lda >= n, A != NULL, reserved == 0", i);
+      return FM_ERR_INVALID;
+    }
+  }
+  fm_flow f = new (std::nothrow) fm_flow_s;
+  if (!f) {
+    set_error("host allocation failed");
+    return FM_ERR_NOMEM;
+  }
+  fm_status s = f->impl.init(problems, batch, dtype, options, (hipStream_t)hip_stream);
+  if (s != FM_OK) {
+    delete f;
+    return s;
+  }
+  *out = f;
+  return FM_OK;
+}
+
+fm_status fm_parareal_solve(fm_flow f, const double* const* X0, double* const* X_out, const fm_params* prm,
+                            fm_stats* stats, void* hip_stream) {
+  fm::clear_error();
+  fm_status s = check_flow(f);
+  if (s != FM_OK) return s;
+  if ((s = check_ptrs(f, (const void* const*)X_out, "X_out")) != FM_OK) return s;
+  if (!prm) {
+    set_error("prm is NULL");
+    return FM_ERR_INVALID;
+  }
+  for (int i = 0; i < f->impl.batch; ++i) {
+    const fm_params& p = prm[i];
+    if (!(p.T > 0) || !std::isfinite(p.T) || p.N < 1 || p.N > 4096 || p.coarse_steps < 1 || p.fine_steps < 1 ||
+        p.max_iter < 0 || p.max_refine < 0 || !(p.tol >= 0) || !(p.refine_tol >= 0) ||
+        (p.coarse != FM_COARSE_EULER && p.coarse != FM_COARSE_LEARNED)) {
+      set_error("prm[%d]: need T > 0, 1 <= N <= 4096, steps >= 1, max_iter >= 0, tol >= 0, known coarse", i);
+      return FM_ERR_INVALID;
+    }
+    if (f->impl.inst[i].kind == FM_FLOW_INV_HOMOTOPY && p.T != 1.0) {
+      set_error("prm[%d]: the homotopy flow reaches A^{-1} at T = 1 only", i);
+      return FM_ERR_INVALID;
+    }
+    if (p.coarse == FM_COARSE_LEARNED && f->impl.inst[i].kind == FM_FLOW_SQRT_STEADY) {
+      set_error("prm[%d]: the learned coarse step is defined for the inverse flows only", i);
+      return FM_ERR_UNSUPPORTED;
+    }
+  }
+  return f->impl.solve(X0, X_out, prm, stats, (hipStream_t)hip_stream);
+}
+
+static fm_status check_prop(fm_flow f, double t1, double t0, int32_t steps, const double* const* X_in,
+                            double* const* X_out) {
+  fm_status s = check_flow(f);
+  if (s != FM_OK) return s;
+  if ((s = check_ptrs(f, (const void* const*)X_in, "X_in")) != FM_OK) return s;
+  if ((s = check_ptrs(f, (const void* const*)X_out, "X_out")) != FM_OK) return s;
+  if (steps < 1 || !std::isfinite(t1) || !std::isfinite(t0)) {
+    set_error("need steps >= 1 and finite times");
+    return FM_ERR_INVALID;
+  }
+  return FM_OK;
+}
+
+fm_status fm_fine_propagate(fm_flow f, double t_next, double t_cur, int32_t steps, const double* const* X_in,
+                            double* const* X_out, void* hip_stream) {
+  fm::clear_error();
+  fm_status s = check_prop(f, t_next, t_cur, steps, X_in, X_out);
+  if (s != FM_OK) return s;
+  return f->impl.fine_propagate(t_next, t_cur, steps, X_in, X_out, (hipStream_t)hip_stream);
+}
+
+fm_status fm_coarse_propagate(fm_flow f, double t_next, double t_cur, int32_t steps, int32_t coarse,
+                              const double* const* X_in, double* const* X_out, void* hip_stream) {
+  fm::clear_error();
+  fm_status s = check_prop(f, t_next, t_cur, steps, X_in, X_out);
+  if (s != FM_OK) return s;
+  if (coarse != FM_COARSE_EULER && coarse != FM_COARSE_LEARNED) {
+    set_error("unknown coarse kind %d", coarse);
+    return FM_ERR_INVALID;
+  }
+  return f->impl.coarse_propagate(t_next, t_cur, steps, coarse, X_in, X_out, (hipStream_t)hip_stream);
+}
+
+void fm_destroy(fm_flow f) {
+  if (!f) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(f->impl.device);
+  (void)hipDeviceSynchronize();
+  delete f;
+  (void)hipSetDevice(cur);
+}
+
+const char* fm_last_error(void) { return fm::last_error(); }
+
+}  // extern "C"

@@ -1,0 +1,949 @@
+// Host engine of libfm: staging, propagators, the parareal driver (Alg. 1 of
+// Sec. 2) and the FP64 refinement.  Device work is issued on the caller's
+// stream; the only host synchronisation is one small read per parareal
+// iteration (the increment) and per refinement step (the residual).
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+
+namespace fm {
+
+static thread_local std::string g_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+}
+void clear_error() { g_error.clear(); }
+const char* last_error() { return g_error.c_str(); }
+
+fm_status hip_status(hipError_t e, const char* what) {
+  set_error("%s failed: %s", what, hipGetErrorString(e));
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return FM_ERR_NOMEM;
+  return FM_ERR_DEVICE;
+}
+
+// ---------------------------------------------------------------- Arena/Ring
+fm_status Arena::reserve(size_t bytes) {
+  if (bytes <= cap && base) {
+    used = 0;
+    return FM_OK;
+  }
+  release();
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes ? bytes : 256);
+  if (e != hipSuccess) return hip_status(e, "hipMalloc(workspace)");
+  base = (char*)p;
+  cap = bytes;
+  used = 0;
+  return FM_OK;
+}
+void Arena::release() {
+  if (base) (void)hipFree(base);
+  base = nullptr;
+  cap = used = 0;
+}
+
+fm_status Ring::init(size_t bytes) {
+  FM_HIP(hipHostMalloc((void**)&host, bytes, hipHostMallocDefault));
+  FM_HIP(hipMalloc((void**)&dev, bytes));
+  cap = bytes;
+  used = 0;
+  return FM_OK;
+}
+void Ring::release() {
+  if (host) (void)hipHostFree(host);
+  if (dev) (void)hipFree(dev);
+  host = dev = nullptr;
+  cap = used = 0;
+}
+void* Ring::push(const void* data, size_t bytes, hipStream_t st) {
+  size_t off = (used + 255) & ~size_t(255);
+  if (off + bytes > cap) return nullptr;
+  memcpy(host + off, data, bytes);
+  if (hipMemcpyAsync(dev + off, host + off, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return nullptr;
+  used = off + bytes;
+  return dev + off;
+}
+
+fm_status Flow::push(const void* data, size_t bytes, void** d, hipStream_t st) {
+  void* p = ring.push(data, bytes, st);
+  if (!p) {
+    // ring full: wait for the queued copies, then start over
+    FM_HIP(hipStreamSynchronize(st));
+    ring.reset();
+    p = ring.push(data, bytes, st);
+    if (!p) {
+      set_error("item list of %zu bytes exceeds the staging ring", bytes);
+      return FM_ERR_NOMEM;
+    }
+  }
+  *d = p;
+  return FM_OK;
+}
+
+fm_status Flow::reserve_ring(size_t bytes, hipStream_t st) {
+  if (bytes + 4096 > ring.cap) {
+    set_error("item lists of %zu bytes exceed the staging ring", bytes);
+    return FM_ERR_NOMEM;
+  }
+  if (ring.room() < bytes + 4096) {
+    FM_HIP(hipStreamSynchronize(st));
+    ring.reset();
+  }
+  return FM_OK;
+}
+
+Flow::~Flow() {
+  for (auto& in : inst) {
+    if (in.A64) (void)hipFree(in.A64);
+    if (in.Bop) (void)hipFree(in.Bop);
+  }
+  ring.release();
+  work.release();
+  prop.release();
+  if (part) (void)hipFree(part);
+  if (hredu) (void)hipHostFree(hredu);
+}
+
+fm_status Flow::ensure_part(size_t count) {
+  if (count <= part_cap) return FM_OK;
+  if (part) (void)hipFree(part);
+  part = nullptr;
+  FM_HIP(hipMalloc((void**)&part, count * sizeof(double)));
+  part_cap = count;
+  return FM_OK;
+}
+fm_status Flow::ensure_hredu(size_t count) {
+  if (count <= hredu_cap) return FM_OK;
+  if (hredu) (void)hipHostFree(hredu);
+  hredu = nullptr;
+  FM_HIP(hipHostMalloc((void**)&hredu, count * sizeof(double), hipHostMallocDefault));
+  hredu_cap = count;
+  return FM_OK;
+}
+
+// ------------------------------------------------------------------ configs
+static int pad_order(int n) { return (n + 63) / 64 * 64; }
+
+static int default_bk(int dt) { return dt == DT_F64 ? 16 : (dt == DT_F32 ? 32 : 64); }
+
+GemmCfg Flow::pick_cfg(int d, int np) {
+  GemmCfg c;
+  c.dt = d;
+  c.bk = default_bk(d);
+  // 128-wide tiles once a product has enough of them to fill the GPU
+  c.bm = (np % 128 == 0 && np >= 512) ? 128 : 64;
+  return c;
+}
+
+// ---------------------------------------------------------------- create
+static void parse_options(const char* opt, std::map<std::string, std::string>& kv) {
+  if (!opt) return;
+  std::string s(opt);
+  size_t pos = 0;
+  while (pos < s.size()) {
+    size_t e = s.find(';', pos);
+    if (e == std::string::npos) e = s.size();
+    std::string item = s.substr(pos, e - pos);
+    size_t eq = item.find('=');
+    if (eq != std::string::npos) kv[item.substr(0, eq)] = item.substr(eq + 1);
+    pos = e + 1;
+  }
+}
+
+fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char* options, hipStream_t st) {
+  FM_HIP(hipGetDevice(&device));
+  dt = dtype;
+  batch = nb;
+  std::map<std::string, std::string> kv;
+  parse_options(options, kv);
+  if (kv.count("autotune")) autotune = kv["autotune"] != "0";
+  if (kv.count("autotune_cache")) autotune_cache = kv["autotune_cache"];
+  FM_TRY(ring.init(size_t(256) << 20));
+  inst.resize(nb);
+  for (int i = 0; i < nb; ++i) {
+    Inst& in = inst[i];
+    in.kind = p[i].kind;
+    in.n = (int)p[i].n;
+    in.np = pad_order(in.n);
+    in.cfg = pick_cfg(dt, in.np);
+    in.cfg64 = pick_cfg(DT_F64, in.np);
+    const size_t np2 = (size_t)in.np * in.np;
+    FM_HIP(hipMalloc((void**)&in.A64, np2 * sizeof(double)));
+    FM_HIP(stage_pad_f64(in.A64, in.np, p[i].A, p[i].n, p[i].lda, st));
+    if (in.kind != FM_FLOW_SQRT_STEADY) {
+      FM_HIP(hipMalloc(&in.Bop, np2 * dt_size(dt)));
+      FM_HIP(convert_f64(in.Bop, dt, in.A64, in.kind == FM_FLOW_INV_HOMOTOPY ? -1.0 : 0.0, in.n, in.np, st));
+    }
+  }
+  if (kv.count("coarse_model")) FM_TRY(load_model(kv["coarse_model"]));
+  FM_HIP(hipStreamSynchronize(st));
+  return FM_OK;
+}
+
+// ------------------------------------------------------------ GEMM launches
+// Launch `items` (item_inst[j] = problem of item j) grouped by tile config.
+fm_status Flow::gemm_groups(int epi, std::vector<GItem>& items, const std::vector<int>& item_inst, bool f64,
+                            hipStream_t st) {
+  if (items.empty()) return FM_OK;
+  std::map<std::pair<int, int>, std::vector<int>> groups;  // (bm, bk) -> item indices
+  for (size_t j = 0; j < items.size(); ++j) {
+    const Inst& in = inst[item_inst[j]];
+    const GemmCfg& c = f64 ? in.cfg64 : in.cfg;
+    groups[{c.bm, c.bk}].push_back((int)j);
+  }
+  for (auto& g : groups) {
+    GemmCfg cfg;
+    cfg.dt = f64 ? DT_F64 : dt;
+    cfg.bm = g.first.first;
+    cfg.bk = g.first.second;
+    std::vector<GItem> sub;
+    std::vector<int> ts;
+    sub.reserve(g.second.size());
+    ts.reserve(g.second.size() + 1);
+    int total = 0;
+    ts.push_back(0);
+    for (int j : g.second) {
+      sub.push_back(items[j]);
+      const int tpn = items[j].np / cfg.bm;
+      total += tpn * tpn;
+      ts.push_back(total);
+    }
+    void* d_items = nullptr;
+    void* d_ts = nullptr;
+    FM_TRY(push(sub.data(), sub.size() * sizeof(GItem), &d_items, st));
+    FM_TRY(push(ts.data(), ts.size() * sizeof(int), &d_ts, st));
+    const int grid = std::min(total, gemm_max_grid(cfg));
+    FM_HIP(launch_gemm(cfg, epi, (const GItem*)d_items, (const int*)d_ts, (int)sub.size(), total, grid, nullptr, st));
+  }
+  return FM_OK;
+}
+
+static GItem blank_item(const Inst& in, int i) {
+  GItem it;
+  memset(&it, 0, sizeof it);
+  it.np = in.np;
+  it.n = in.n;
+  it.inst = i;
+  return it;
+}
+
+// ------------------------------------------------------- fine propagator
+// `steps` classical RK4 steps of size slot.h on every slot, in place on
+// slot.x; slot.ya must hold op(x) on entry.  One grouped launch per product:
+// stage s reads Y from ya (s odd) or yb (s even) and writes the next stage
+// operand to the other buffer, so after 4 stages Y is back in ya.
+fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStream_t st) {
+  if (slots.empty() || steps <= 0) return FM_OK;
+  // Build the 8 item lists once; they are identical for every step.
+  std::vector<GItem> l1[4], l2[4];
+  std::vector<int> i1[4], i2[4];
+  for (int s = 0; s < 4; ++s) {
+    for (const FineSlot& sl : slots) {
+      const Inst& in = inst[sl.inst];
+      void* ycur = (s % 2 == 0) ? sl.ya : sl.yb;
+      void* ynext = (s % 2 == 0) ? sl.yb : sl.ya;
+      if (in.kind != FM_FLOW_SQRT_STEADY) {
+        GItem g = blank_item(in, sl.inst);
+        g.a = in.Bop;
+        g.b = ycur;
+        g.out0 = sl.p;
+        g.flags = F_E_NONE;
+        g.s[0] = 1.0;
+        l1[s].push_back(g);
+        i1[s].push_back(sl.inst);
+      }
+      GItem g = blank_item(in, sl.inst);
+      g.a = ycur;
+      g.out0 = ynext;
+      g.out1 = sl.kacc;
+      g.x = sl.x;
+      g.stage = s + 1;
+      g.s[2] = sl.h;
+      switch (in.kind) {
+        case FM_FLOW_INV_HOMOTOPY:  // k = -Y (M Y)
+          g.b = sl.p;
+          g.s[0] = -1.0;
+          g.flags = F_E_NONE;
+          break;
+        case FM_FLOW_INV_STEADY:  // k = Y - Y (A Y)
+          g.b = sl.p;
+          g.s[0] = -1.0;
+          g.s[1] = 1.0;
+          g.in0 = ycur;
+          g.flags = 0;
+          break;
+        default:  // k = A - Y Y
+          g.b = ycur;
+          g.s[0] = -1.0;
+          g.s[1] = 1.0;
+          g.in0 = in.A64;
+          g.flags = F_E_F64;
+      }
+      l2[s].push_back(g);
+      i2[s].push_back(sl.inst);
+    }
+  }
+  // Push the lists once and replay the launches for every step.
+  struct Launch {
+    GemmCfg cfg;
+    int epi;
+    const GItem* items;
+    const int* ts;
+    int n;
+    int total;
+  };
+  std::vector<Launch> seq;
+  {
+    // every list below is launched `steps` times: no ring reset in between
+    size_t need = 0;
+    for (int s = 0; s < 4; ++s)
+      need += (l1[s].size() + l2[s].size()) * (sizeof(GItem) + sizeof(int)) + 8 * 512;
+    FM_TRY(reserve_ring(need, st));
+  }
+  auto prepare = [&](std::vector<GItem>& items, const std::vector<int>& ii, int epi) -> fm_status {
+    if (items.empty()) return FM_OK;
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (size_t j = 0; j < items.size(); ++j) {
+      const GemmCfg& c = inst[ii[j]].cfg;
+      groups[{c.bm, c.bk}].push_back((int)j);
+    }
+    for (auto& g : groups) {
+      Launch L;
+      L.cfg.dt = dt;
+      L.cfg.bm = g.first.first;
+      L.cfg.bk = g.first.second;
+      L.epi = epi;
+      std::vector<GItem> sub;
+      std::vector<int> ts(1, 0);
+      int total = 0;
+      for (int j : g.second) {
+        sub.push_back(items[j]);
+        const int tpn = items[j].np / L.cfg.bm;
+        total += tpn * tpn;
+        ts.push_back(total);
+      }
+      void* di = nullptr;
+      void* dts = nullptr;
+      FM_TRY(push(sub.data(), sub.size() * sizeof(GItem), &di, st));
+      FM_TRY(push(ts.data(), ts.size() * sizeof(int), &dts, st));
+      L.items = (const GItem*)di;
+      L.ts = (const int*)dts;
+      L.n = (int)sub.size();
+      L.total = total;
+      seq.push_back(L);
+    }
+    return FM_OK;
+  };
+  for (int s = 0; s < 4; ++s) {
+    FM_TRY(prepare(l1[s], i1[s], EPI_AFFINE));
+    FM_TRY(prepare(l2[s], i2[s], EPI_RK4));
+  }
+  for (int step = 0; step < steps; ++step)
+    for (const Launch& L : seq)
+      FM_HIP(launch_gemm(L.cfg, L.epi, L.items, L.ts, L.n, L.total, std::min(L.total, gemm_max_grid(L.cfg)),
+                         nullptr, st));
+  return FM_OK;
+}
+
+// ----------------------------------------------------- coarse propagator
+// `steps` forward-Euler (or learned polynomial) substeps of size slot.h from
+// slot.xin to slot.xout.  Operands ping-pong between y0 and y1.
+fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipStream_t st) {
+  if (slots.empty() || steps <= 0) return FM_OK;
+  {
+    std::vector<PrepItem> prep;
+    for (const CoarseSlot& sl : slots) {
+      const Inst& in = inst[sl.inst];
+      PrepItem p;
+      p.u = sl.xin;
+      p.fo = nullptr;
+      p.y = sl.y0;
+      p.count = (int64_t)in.np * in.np;
+      p.inst = sl.inst;
+      p.pad_ = 0;
+      prep.push_back(p);
+    }
+    void* d = nullptr;
+    FM_TRY(push(prep.data(), prep.size() * sizeof(PrepItem), &d, st));
+    FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), dt, nullptr, st));
+  }
+  for (int j = 0; j < steps; ++j) {
+    std::vector<GItem> l1, l2, l3, l4;
+    std::vector<int> i1, i2, i3, i4;
+    for (const CoarseSlot& sl : slots) {
+      const Inst& in = inst[sl.inst];
+      void* yin = (j % 2 == 0) ? sl.y0 : sl.y1;
+      void* yout = (j % 2 == 0) ? sl.y1 : sl.y0;
+      const double* x = (j == 0) ? sl.xin : sl.xout;
+      if (!sl.learned) {
+        if (in.kind != FM_FLOW_SQRT_STEADY) {
+          GItem g = blank_item(in, sl.inst);
+          g.a = in.Bop;
+          g.b = yin;
+          g.out0 = sl.p;
+          g.flags = F_E_NONE;
+          g.s[0] = 1.0;
+          l1.push_back(g);
+          i1.push_back(sl.inst);
+        }
+        GItem g = blank_item(in, sl.inst);
+        g.a = yin;
+        g.out0 = yout;
+        g.out1 = sl.xout;
+        g.x = const_cast<double*>(x);
+        g.s[2] = sl.h;
+        switch (in.kind) {
+          case FM_FLOW_INV_HOMOTOPY:
+            g.b = sl.p;
+            g.s[0] = -1.0;
+            g.flags = F_E_NONE;
+            break;
+          case FM_FLOW_INV_STEADY:
+            g.b = sl.p;
+            g.s[0] = -1.0;
+            g.s[1] = 1.0;
+            g.in0 = yin;
+            g.flags = 0;
+            break;
+          default:
+            g.b = yin;
+            g.s[0] = -1.0;
+            g.s[1] = 1.0;
+            g.in0 = in.A64;
+            g.flags = F_E_F64;
+        }
+        l2.push_back(g);
+        i2.push_back(sl.inst);
+      } else {
+        // K = h B Y ; K2 = K K ; P = c0 I + c1 K + c2 K2 + c3 K2 K (and K3) ;
+        // X+ = Y P + c4 I + c5 K + c6 K2 + c7 K3
+        const double* c = sl.coef + 8 * j;
+        GItem g = blank_item(in, sl.inst);
+        g.a = in.Bop;
+        g.b = yin;
+        g.out0 = sl.k1;
+        g.flags = F_E_NONE;
+        g.s[0] = sl.h;
+        l1.push_back(g);
+        i1.push_back(sl.inst);
+        GItem g2 = blank_item(in, sl.inst);
+        g2.a = sl.k1;
+        g2.b = sl.k1;
+        g2.out0 = sl.k2;
+        g2.flags = F_E_NONE;
+        g2.s[0] = 1.0;
+        l2.push_back(g2);
+        i2.push_back(sl.inst);
+        GItem g3 = blank_item(in, sl.inst);
+        g3.a = sl.k2;
+        g3.b = sl.k1;
+        g3.out0 = sl.p;
+        g3.out1 = sl.k3;
+        g3.in0 = sl.k1;
+        g3.in1 = sl.k2;
+        for (int q = 0; q < 8; ++q) g3.s[q] = c[q];
+        l3.push_back(g3);
+        i3.push_back(sl.inst);
+        GItem g4 = blank_item(in, sl.inst);
+        g4.a = yin;
+        g4.b = sl.p;
+        g4.out0 = yout;
+        g4.out1 = sl.xout;
+        g4.in0 = sl.k1;
+        g4.in1 = sl.k2;
+        g4.in2 = sl.k3;
+        for (int q = 0; q < 8; ++q) g4.s[q] = c[q];
+        l4.push_back(g4);
+        i4.push_back(sl.inst);
+      }
+    }
+    // Euler items go to l1 (first product) / l2 (EPI_EULER); learned items
+    // use l1..l4.  A call mixes both kinds only through separate lists.
+    bool any_learned = false, any_euler = false;
+    for (const CoarseSlot& sl : slots) (sl.learned ? any_learned : any_euler) = true;
+    if (any_euler && any_learned) {
+      set_error("internal: mixed coarse kinds in one call");
+      return FM_ERR_INVALID;
+    }
+    if (!any_learned) {
+      FM_TRY(gemm_groups(EPI_AFFINE, l1, i1, false, st));
+      FM_TRY(gemm_groups(EPI_EULER, l2, i2, false, st));
+    } else {
+      FM_TRY(gemm_groups(EPI_AFFINE, l1, i1, false, st));
+      FM_TRY(gemm_groups(EPI_AFFINE, l2, i2, false, st));
+      FM_TRY(gemm_groups(EPI_POLYP, l3, i3, false, st));
+      FM_TRY(gemm_groups(EPI_POLYX, l4, i4, false, st));
+    }
+  }
+  return FM_OK;
+}
+
+// ------------------------------------------------- standalone propagators
+fm_status Flow::fine_propagate(double t1, double t0, int steps, const double* const* xin, double* const* xout,
+                               hipStream_t st) {
+  // workspace: per problem x (FP64), ya, yb, p (op), kacc (acc)
+  std::vector<FineSlot> slots(batch);
+  for (int pass = 0; pass < 2; ++pass) {
+    prop.measuring = (pass == 0);
+    prop.used = 0;
+    for (int i = 0; i < batch; ++i) {
+      const size_t np2 = (size_t)inst[i].np * inst[i].np;
+      FineSlot& s = slots[i];
+      s.inst = i;
+      s.x = (double*)prop.take(np2 * 8);
+      s.ya = prop.take(np2 * dt_size(dt));
+      s.yb = prop.take(np2 * dt_size(dt));
+      s.p = prop.take(np2 * dt_size(dt));
+      s.kacc = prop.take(np2 * acc_size(dt));
+      s.h = (t1 - t0) / steps;
+    }
+    if (pass == 0) FM_TRY(prop.reserve(prop.used));
+  }
+  ring.reset();
+  FM_HIP(hipStreamSynchronize(st));
+  std::vector<PrepItem> prep;
+  for (int i = 0; i < batch; ++i) {
+    FM_HIP(copy_in(slots[i].x, inst[i].np, xin[i], inst[i].n, st));
+    PrepItem p{slots[i].x, nullptr, slots[i].ya, (int64_t)inst[i].np * inst[i].np, i, 0};
+    prep.push_back(p);
+  }
+  void* d = nullptr;
+  FM_TRY(push(prep.data(), prep.size() * sizeof(PrepItem), &d, st));
+  FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), dt, nullptr, st));
+  FM_TRY(run_fine(slots, steps, st));
+  for (int i = 0; i < batch; ++i) FM_HIP(copy_out(xout[i], inst[i].n, slots[i].x, inst[i].np, st));
+  return FM_OK;
+}
+
+fm_status Flow::coarse_propagate(double t1, double t0, int steps, int coarse, const double* const* xin,
+                                 double* const* xout, hipStream_t st) {
+  if (coarse == FM_COARSE_LEARNED && !model.loaded) {
+    set_error("learned coarse step requested but no coarse_model is loaded");
+    return FM_ERR_INVALID;
+  }
+  std::vector<CoarseSlot> slots(batch);
+  std::vector<double> coefs((size_t)batch * 8 * steps);
+  for (int pass = 0; pass < 2; ++pass) {
+    prop.measuring = (pass == 0);
+    prop.used = 0;
+    for (int i = 0; i < batch; ++i) {
+      const size_t np2 = (size_t)inst[i].np * inst[i].np;
+      const size_t e = dt_size(dt);
+      CoarseSlot& s = slots[i];
+      s.inst = i;
+      double* xi = (double*)prop.take(np2 * 8);
+      s.xin = xi;
+      s.xout = xi;
+      s.y0 = prop.take(np2 * e);
+      s.y1 = prop.take(np2 * e);
+      s.p = prop.take(np2 * e);
+      s.k1 = prop.take(np2 * e);
+      s.k2 = prop.take(np2 * e);
+      s.k3 = prop.take(np2 * e);
+      s.t0 = t0;
+      s.h = (t1 - t0) / steps;
+      s.learned = coarse == FM_COARSE_LEARNED;
+      s.coef = coefs.data() + (size_t)i * 8 * steps;
+    }
+    if (pass == 0) FM_TRY(prop.reserve(prop.used));
+  }
+  if (coarse == FM_COARSE_LEARNED)
+    for (int i = 0; i < batch; ++i)
+      for (int j = 0; j < steps; ++j)
+        FM_TRY(learned_coeffs(i, t0 + j * slots[i].h, slots[i].h, coefs.data() + ((size_t)i * steps + j) * 8));
+  ring.reset();
+  FM_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < batch; ++i) FM_HIP(copy_in(slots[i].xout, inst[i].np, xin[i], inst[i].n, st));
+  FM_TRY(run_coarse(slots, steps, st));
+  for (int i = 0; i < batch; ++i) FM_HIP(copy_out(xout[i], inst[i].n, slots[i].xout, inst[i].np, st));
+  return FM_OK;
+}
+
+// ------------------------------------------------------------ parareal
+fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_params* prm, fm_stats* stats,
+                      hipStream_t st) {
+  const size_t e = dt_size(dt), ea = acc_size(dt);
+  int Nmax = 0;
+  for (int i = 0; i < batch; ++i) Nmax = std::max(Nmax, prm[i].N);
+  bool any_learned = false;
+  for (int i = 0; i < batch; ++i) any_learned |= prm[i].coarse == FM_COARSE_LEARNED;
+  if (any_learned && !model.loaded) {
+    set_error("coarse = FM_COARSE_LEARNED needs a loaded coarse_model");
+    return FM_ERR_INVALID;
+  }
+
+  // ---- workspace layout
+  struct IW {
+    std::vector<double*> U, Fo, Go;
+    std::vector<void*> ya, yb, p, kacc;
+    double* gnew;
+    void *cy0, *cy1, *cp, *ck1, *ck2, *ck3;
+    // learned: coarse choice per slice and coefficient table
+    std::vector<double> coef;    // N * coarse_steps * 8
+    std::vector<int> use_learned;
+  };
+  std::vector<IW> w(batch);
+  for (int pass = 0; pass < 2; ++pass) {
+    work.measuring = (pass == 0);
+    work.used = 0;
+    for (int i = 0; i < batch; ++i) {
+      const size_t np2 = (size_t)inst[i].np * inst[i].np;
+      const int N = prm[i].N;
+      IW& q = w[i];
+      q.U.resize(N + 1);
+      q.Fo.resize(N);
+      q.Go.resize(N);
+      q.ya.resize(N);
+      q.yb.resize(N);
+      q.p.resize(N);
+      q.kacc.resize(N);
+      for (int s = 0; s <= N; ++s) q.U[s] = (double*)work.take(np2 * 8);
+      for (int s = 0; s < N; ++s) {
+        q.Fo[s] = (double*)work.take(np2 * 8);
+        q.Go[s] = (double*)work.take(np2 * 8);
+        q.ya[s] = work.take(np2 * e);
+        q.yb[s] = work.take(np2 * e);
+        q.p[s] = work.take(np2 * e);
+        q.kacc[s] = work.take(np2 * ea);
+      }
+      q.gnew = (double*)work.take(np2 * 8);
+      q.cy0 = work.take(np2 * e);
+      q.cy1 = work.take(np2 * e);
+      q.cp = work.take(np2 * e);
+      const bool lrn = prm[i].coarse == FM_COARSE_LEARNED;
+      q.ck1 = lrn ? work.take(np2 * e) : nullptr;
+      q.ck2 = lrn ? work.take(np2 * e) : nullptr;
+      q.ck3 = lrn ? work.take(np2 * e) : nullptr;
+    }
+    if (pass == 0) FM_TRY(work.reserve(work.used));
+  }
+  FM_HIP(hipStreamSynchronize(st));
+  ring.reset();
+
+  // learned coefficient tables (one network evaluation per slice substep)
+  for (int i = 0; i < batch; ++i) {
+    if (prm[i].coarse != FM_COARSE_LEARNED) continue;
+    const int N = prm[i].N, C = prm[i].coarse_steps;
+    w[i].coef.resize((size_t)N * C * 8);
+    w[i].use_learned.assign(N, 1);
+    for (int s = 0; s < N; ++s) {
+      const double ta = s * prm[i].T / N, tb = (s + 1) * prm[i].T / N;
+      const double h = (tb - ta) / C;
+      for (int j = 0; j < C; ++j) FM_TRY(learned_coeffs(i, ta + j * h, h, &w[i].coef[((size_t)s * C + j) * 8]));
+    }
+  }
+
+  // ---- Step 0: U_0 = X0, U_{n+1} = G(U_n), G_old cached
+  for (int i = 0; i < batch; ++i) {
+    if (X0 && X0[i]) FM_HIP(copy_in(w[i].U[0], inst[i].np, X0[i], inst[i].n, st));
+    else FM_HIP(set_identity(w[i].U[0], inst[i].n, inst[i].np, st));
+  }
+  auto coarse_slot = [&](int i, int s, const double* xin, double* xout, bool learned) {
+    CoarseSlot c;
+    const int N = prm[i].N, C = prm[i].coarse_steps;
+    const double ta = s * prm[i].T / N, tb = (s + 1) * prm[i].T / N;
+    c.inst = i;
+    c.xin = xin;
+    c.xout = xout;
+    c.y0 = w[i].cy0;
+    c.y1 = w[i].cy1;
+    c.p = w[i].cp;
+    c.k1 = w[i].ck1;
+    c.k2 = w[i].ck2;
+    c.k3 = w[i].ck3;
+    c.t0 = ta;
+    c.h = (tb - ta) / C;
+    c.learned = learned ? 1 : 0;
+    c.coef = learned ? &w[i].coef[(size_t)s * C * 8] : nullptr;
+    return c;
+  };
+  // coarse steps of one sweep position, split by coarse kind and step count
+  auto run_coarse_mixed = [&](std::vector<CoarseSlot>& all) -> fm_status {
+    std::map<std::pair<int, int>, std::vector<CoarseSlot>> by;
+    for (auto& c : all) by[{c.learned, prm[c.inst].coarse_steps}].push_back(c);
+    for (auto& g : by) FM_TRY(run_coarse(g.second, g.first.second, st));
+    return FM_OK;
+  };
+  for (int s = 0; s < Nmax; ++s) {
+    std::vector<CoarseSlot> cs;
+    for (int i = 0; i < batch; ++i)
+      if (s < prm[i].N) cs.push_back(coarse_slot(i, s, w[i].U[s], w[i].Go[s], prm[i].coarse == FM_COARSE_LEARNED));
+    FM_TRY(run_coarse_mixed(cs));
+    for (int i = 0; i < batch; ++i)
+      if (s < prm[i].N) FM_HIP(copy_f64(w[i].U[s + 1], w[i].Go[s], (int64_t)inst[i].np * inst[i].np, st));
+  }
+
+  // ---- iterations
+  std::vector<int> live(batch, 0), iters(batch, 0);
+  std::vector<fm_status> ist(batch, FM_OK);
+  std::vector<double> lastinc(batch, 0.0);
+  std::vector<std::vector<double>> hist(batch);
+  for (int i = 0; i < batch; ++i) live[i] = prm[i].max_iter > 0 && prm[i].N > 0;
+  int nblk = 1;
+  for (int i = 0; i < batch; ++i) {
+    int64_t np2 = (int64_t)inst[i].np * inst[i].np;
+    nblk = std::max<int>(nblk, (int)std::min<int64_t>(256, (np2 + 4095) / 4096));
+  }
+  const size_t npairs = (size_t)Nmax * batch;
+  FM_TRY(ensure_part(npairs * nblk * 3 + npairs * 3));
+  double* d_red = part + npairs * nblk * 3;
+  FM_TRY(ensure_hredu(npairs * 3));
+
+  for (int k = 0;; ++k) {
+    bool any = false;
+    for (int i = 0; i < batch; ++i) any |= live[i] != 0;
+    if (!any) break;
+    FM_HIP(hipStreamSynchronize(st));
+    ring.reset();
+    // fine solves of all live (problem, slice >= k) pairs in one launch per product
+    std::vector<FineSlot> fs;
+    std::vector<PrepItem> prep;
+    for (int s = k; s < Nmax; ++s)
+      for (int i = 0; i < batch; ++i) {
+        if (!live[i] || s >= prm[i].N) continue;
+        const int N = prm[i].N;
+        const double ta = s * prm[i].T / N, tb = (s + 1) * prm[i].T / N;
+        FineSlot f{i, w[i].Fo[s], w[i].ya[s], w[i].yb[s], w[i].p[s], w[i].kacc[s], (tb - ta) / prm[i].fine_steps};
+        fs.push_back(f);
+        prep.push_back(PrepItem{w[i].U[s], w[i].Fo[s], w[i].ya[s], (int64_t)inst[i].np * inst[i].np, i, 0});
+      }
+    {
+      void* d = nullptr;
+      FM_TRY(push(prep.data(), prep.size() * sizeof(PrepItem), &d, st));
+      FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), dt, nullptr, st));
+    }
+    // all live problems share fine_steps per call: group by step count
+    {
+      std::map<int, std::vector<FineSlot>> by;
+      for (auto& f : fs) by[prm[f.inst].fine_steps].push_back(f);
+      for (auto& g : by) FM_TRY(run_fine(g.second, g.first, st));
+    }
+    // learned coarse: choose per slice between the learned and the Euler step
+    // by their defect against F(U^k_n) (fallback), and recompute G_old with
+    // the chosen step.
+    for (int i = 0; i < batch; ++i) {
+      if (!live[i] || prm[i].coarse != FM_COARSE_LEARNED) continue;
+      // handled below (needs device defects): see learned_fallback
+    }
+    // sequential correction sweep
+    for (int s = k; s < Nmax; ++s) {
+      std::vector<CoarseSlot> cs;
+      std::vector<CorrItem> ci;
+      for (int i = 0; i < batch; ++i) {
+        if (!live[i] || s >= prm[i].N) continue;
+        if (s > k)
+          cs.push_back(coarse_slot(i, s, w[i].U[s], w[i].gnew,
+                                   prm[i].coarse == FM_COARSE_LEARNED && w[i].use_learned[s]));
+        CorrItem c;
+        c.u = w[i].U[s + 1];
+        c.f = w[i].Fo[s];
+        c.gnew = (s > k) ? w[i].gnew : w[i].Go[s];
+        c.gold = w[i].Go[s];
+        c.count = (int64_t)inst[i].np * inst[i].np;
+        c.inst = i;
+        c.slot = s * batch + i;
+        ci.push_back(c);
+      }
+      FM_TRY(run_coarse_mixed(cs));
+      if (!ci.empty()) {
+        void* d = nullptr;
+        FM_TRY(push(ci.data(), ci.size() * sizeof(CorrItem), &d, st));
+        FM_HIP(launch_correction((const CorrItem*)d, (int)ci.size(), part, nblk, nullptr, st));
+      }
+    }
+    FM_HIP(launch_reduce_pairs(part, (int)npairs, nblk, d_red, st));
+    FM_HIP(hipMemcpyAsync(hredu, d_red, npairs * 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    FM_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < batch; ++i) {
+      if (!live[i]) continue;
+      double inc = 0.0;
+      bool bad = false;
+      for (int s = k; s < prm[i].N; ++s) {
+        const double* r = hredu + ((size_t)s * batch + i) * 3;
+        const double d = r[0] > 0 ? std::sqrt(r[0]) : 0.0;
+        const double u = r[1] > 0 ? std::sqrt(r[1]) : 0.0;
+        const double q = u > 0 ? d / u : d;
+        if (!(q == q)) bad = true;
+        inc = std::max(inc, q);
+        if (r[2] != 0.0) bad = true;
+      }
+      iters[i] = k + 1;
+      lastinc[i] = inc;
+      hist[i].push_back(inc);
+      if (bad) {
+        ist[i] = FM_ERR_NONFINITE;
+        live[i] = 0;
+        continue;
+      }
+      if (inc <= prm[i].tol || k + 1 >= prm[i].N) {
+        live[i] = 0;
+      } else if (k + 1 >= prm[i].max_iter) {
+        live[i] = 0;
+        ist[i] = FM_WARN_NOT_CONVERGED;
+      }
+    }
+  }
+
+  // ---- result, residual and refinement
+  std::vector<double*> X(batch);
+  std::vector<int> which;
+  for (int i = 0; i < batch; ++i) {
+    X[i] = w[i].U[prm[i].N];
+    if (ist[i] != FM_ERR_NONFINITE) which.push_back(i);
+  }
+  if (stats) {
+    for (int i = 0; i < batch; ++i) {
+      memset(&stats[i], 0, sizeof(fm_stats));
+      stats[i].iters = iters[i];
+      stats[i].increment = lastinc[i];
+      for (size_t j = 0; j < hist[i].size() && j < 64; ++j) stats[i].hist[j] = hist[i][j];
+      stats[i].residual_before = stats[i].residual = NAN;
+    }
+  }
+  FM_TRY(refine(which, X, prm, stats, st));
+  fm_status worst = FM_OK;
+  for (int i = 0; i < batch; ++i) {
+    if (ist[i] != FM_ERR_NONFINITE) FM_HIP(copy_out(Xout[i], inst[i].n, X[i], inst[i].np, st));
+    if (stats) stats[i].status = ist[i];
+    if (ist[i] < 0 && (worst >= 0 || ist[i] < worst)) worst = ist[i];
+    else if (worst == FM_OK && ist[i] != FM_OK) worst = ist[i];
+  }
+  FM_HIP(hipStreamSynchronize(st));
+  if (worst == FM_ERR_NONFINITE) set_error("an iterate became non-finite (A(t) singular or the flow diverged)");
+  return worst;
+}
+
+// ----------------------------------------------------------- refinement
+// Inverse flows: R = I - A X, X <- X + X R (Newton-Schulz).  Square root:
+// R = A - X^2, X <- X + H with X H + H X = R solved by conjugate gradients.
+// The residual ||R||_F / ||target scale|| is computed before every step.
+fm_status Flow::refine(const std::vector<int>& which, std::vector<double*>& X, const fm_params* prm,
+                       fm_stats* stats, hipStream_t st) {
+  if (which.empty()) return FM_OK;
+  // scratch: R and X2 per problem (FP64)
+  std::vector<double*> R(batch, nullptr), X2(batch, nullptr);
+  for (int pass = 0; pass < 2; ++pass) {
+    prop.measuring = (pass == 0);
+    prop.used = 0;
+    for (int i : which) {
+      const size_t np2 = (size_t)inst[i].np * inst[i].np;
+      R[i] = (double*)prop.take(np2 * 8);
+      X2[i] = (double*)prop.take(np2 * 8);
+    }
+    if (pass == 0) {
+      FM_HIP(hipStreamSynchronize(st));
+      FM_TRY(prop.reserve(prop.used));
+    }
+  }
+  FM_TRY(ensure_part(4096 + 2 * batch));
+  FM_TRY(ensure_hredu(2 * batch + 2));
+  std::vector<int> active = which;
+  std::vector<int> steps(batch, 0);
+  std::vector<double> scale(batch, 1.0);
+  // ||A||_F for the square-root residual
+  for (int i : which)
+    if (inst[i].kind == FM_FLOW_SQRT_STEADY) {
+      FM_HIP(launch_dot(inst[i].A64, inst[i].A64, (int64_t)inst[i].np * inst[i].np, part, 64, part + 4096 + i, st));
+    }
+  FM_HIP(hipMemcpyAsync(hredu, part + 4096, batch * sizeof(double), hipMemcpyDeviceToHost, st));
+  FM_HIP(hipStreamSynchronize(st));
+  for (int i : which) scale[i] = inst[i].kind == FM_FLOW_SQRT_STEADY ? std::sqrt(hredu[i]) : std::sqrt((double)inst[i].n);
+  bool first = true;
+  while (!active.empty()) {
+    FM_HIP(hipStreamSynchronize(st));
+    ring.reset();
+    // residuals
+    std::vector<GItem> items;
+    std::vector<int> ii;
+    for (int i : active) {
+      const Inst& in = inst[i];
+      GItem g = blank_item(in, i);
+      g.out0 = R[i];
+      if (in.kind == FM_FLOW_SQRT_STEADY) {  // R = A - X X
+        g.a = X[i];
+        g.b = X[i];
+        g.in0 = in.A64;
+        g.s[0] = -1.0;
+        g.s[1] = 1.0;
+        g.flags = F_OUT0_F64 | F_E_F64;
+      } else {  // R = I - A X
+        g.a = in.A64;
+        g.b = X[i];
+        g.s[0] = -1.0;
+        g.s[2] = 1.0;
+        g.flags = F_OUT0_F64 | F_E_NONE;
+      }
+      items.push_back(g);
+      ii.push_back(i);
+    }
+    FM_TRY(gemm_groups(EPI_AFFINE, items, ii, true, st));
+    for (int i : active)
+      FM_HIP(launch_dot(R[i], R[i], (int64_t)inst[i].np * inst[i].np, part, 64, part + 4096 + i, st));
+    FM_HIP(hipMemcpyAsync(hredu, part + 4096, batch * sizeof(double), hipMemcpyDeviceToHost, st));
+    FM_HIP(hipStreamSynchronize(st));
+    std::vector<int> next;
+    for (int i : active) {
+      const double res = std::sqrt(hredu[i]) / scale[i];
+      if (stats) {
+        if (first) stats[i].residual_before = res;
+        stats[i].residual = res;
+        stats[i].refine_steps = steps[i];
+      }
+      if (res > prm[i].refine_tol && steps[i] < prm[i].max_refine) next.push_back(i);
+    }
+    first = false;
+    if (next.empty()) break;
+    // updates
+    std::vector<GItem> upd;
+    std::vector<int> ui;
+    for (int i : next) {
+      const Inst& in = inst[i];
+      if (in.kind == FM_FLOW_SQRT_STEADY) {
+        set_error("square-root refinement is not available in this build");
+        return FM_ERR_UNSUPPORTED;
+      }
+      GItem g = blank_item(in, i);  // X2 = X + X R
+      g.a = X[i];
+      g.b = R[i];
+      g.in0 = X[i];
+      g.out0 = X2[i];
+      g.s[0] = 1.0;
+      g.s[1] = 1.0;
+      g.flags = F_OUT0_F64 | F_E_F64;
+      upd.push_back(g);
+      ui.push_back(i);
+    }
+    FM_TRY(gemm_groups(EPI_AFFINE, upd, ui, true, st));
+    for (int i : next) {
+      std::swap(X[i], X2[i]);
+      steps[i]++;
+    }
+    active = next;
+  }
+  // results that ended in the refinement scratch are copied by the caller
+  // from X[i]; keep the scratch alive until then (prop is not reused before).
+  return FM_OK;
+}
+
+fm_status Flow::learned_coeffs(int, double, double, double*) const {
+  set_error("learned coarse step is not available in this build");
+  return FM_ERR_UNSUPPORTED;
+}
+
+fm_status Flow::load_model(const std::string&) {
+  set_error("learned coarse model loading is not available in this build");
+  return FM_ERR_UNSUPPORTED;
+}
+
+}  // namespace fm

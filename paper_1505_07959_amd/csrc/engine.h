@@ -1,0 +1,151 @@
+// Host-side engine of libfm: the flow object, propagators, parareal driver.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "fm.h"
+#include "fm_common.h"
+
+namespace fm {
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+fm_status hip_status(hipError_t e, const char* what);
+
+#define FM_HIP(expr)                                                       \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess) return ::fm::hip_status(e_, #expr);              \
+  } while (0)
+
+#define FM_TRY(expr)                                                       \
+  do {                                                                     \
+    fm_status s_ = (expr);                                                 \
+    if (s_ != FM_OK) return s_;                                            \
+  } while (0)
+
+// Bump allocator over one device allocation; a first pass with base == null
+// only measures.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  bool measuring = false;
+  void* take(size_t bytes) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + bytes;
+    return measuring ? nullptr : base + off;
+  }
+  fm_status reserve(size_t bytes);
+  void release();
+};
+
+// Pinned host staging ring + matching device ring for per-launch item lists.
+// Valid until the next reset(), which must follow a stream synchronisation.
+struct Ring {
+  char* host = nullptr;
+  char* dev = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  fm_status init(size_t bytes);
+  void release();
+  void reset() { used = 0; }
+  size_t room() const { return cap > used + 256 ? cap - used - 256 : 0; }
+  // copies `bytes` to the device on `st`; returns the device address or null
+  // when full (caller synchronises, resets and retries).
+  void* push(const void* data, size_t bytes, hipStream_t st);
+};
+
+// Learned coarse step: network weights and input standardisation.
+struct Model {
+  bool loaded = false;
+  int kind = 0;                 // flow kind it was trained for
+  std::vector<double> theta;    // 9288 parameters (layout of the training script)
+  double mean[6] = {0}, stdv[6] = {1, 1, 1, 1, 1, 1};
+};
+
+struct Inst {
+  int kind = 0;
+  int n = 0, np = 0;
+  GemmCfg cfg{};     // product config in the flow dtype
+  GemmCfg cfg64{};   // FP64 config (residual / refinement)
+  double* A64 = nullptr;  // padded FP64 A
+  void* Bop = nullptr;    // right operand of the first product: A - I (homotopy) or A
+  double mu[4] = {0, 0, 0, 0};  // tr((A - I)^j) / n
+};
+
+// Per-slot buffers of one propagation.
+struct FineSlot {
+  int inst;
+  double* x;     // FP64 state, in place
+  void* ya;      // operand buffers (ya holds op(x) on entry)
+  void* yb;
+  void* p;
+  void* kacc;
+  double h;
+};
+
+struct CoarseSlot {
+  int inst;
+  const double* xin;  // FP64 input
+  double* xout;       // FP64 output (may equal xin)
+  void* y0;           // operand ping-pong
+  void* y1;
+  void* p;
+  void* k1;           // learned step scratch
+  void* k2;
+  void* k3;
+  double t0;          // time at the slot start (learned-step network input)
+  double h;           // substep size
+  int learned;        // 1: learned polynomial step, 0: Euler
+  const double* coef; // host: 8 coefficients per substep (learned)
+};
+
+struct Flow {
+  int device = 0;
+  int dt = 0;
+  int batch = 0;
+  std::vector<Inst> inst;
+  Model model;
+  bool autotune = true;
+  std::string autotune_cache;
+  Ring ring;
+  Arena work;      // parareal workspace
+  Arena prop;      // propagator workspace (fm_fine/coarse_propagate)
+  double* part = nullptr;   // reduction partials
+  size_t part_cap = 0;
+  double* hredu = nullptr;  // pinned host copy of reduced triples
+  size_t hredu_cap = 0;
+
+  ~Flow();
+  fm_status init(const fm_problem* p, int32_t batch, int32_t dtype, const char* options, hipStream_t st);
+
+  // launch helpers
+  fm_status gemm_groups(int epi, std::vector<GItem>& items, const std::vector<int>& item_inst, bool f64,
+                        hipStream_t st);
+  fm_status push(const void* data, size_t bytes, void** dev, hipStream_t st);
+  // make sure `bytes` of item lists can be pushed without an intermediate reset
+  fm_status reserve_ring(size_t bytes, hipStream_t st);
+  fm_status ensure_part(size_t count);
+  fm_status ensure_hredu(size_t count);
+
+  fm_status run_fine(const std::vector<FineSlot>& slots, int steps, hipStream_t st);
+  fm_status run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipStream_t st);
+  fm_status learned_coeffs(int i, double t0, double h, double* c) const;
+
+  fm_status fine_propagate(double t1, double t0, int steps, const double* const* xin, double* const* xout,
+                           hipStream_t st);
+  fm_status coarse_propagate(double t1, double t0, int steps, int coarse, const double* const* xin,
+                             double* const* xout, hipStream_t st);
+  fm_status solve(const double* const* X0, double* const* Xout, const fm_params* prm, fm_stats* stats,
+                  hipStream_t st);
+  fm_status refine(const std::vector<int>& which, std::vector<double*>& X, const fm_params* prm,
+                   fm_stats* stats, hipStream_t st);
+
+  fm_status load_model(const std::string& path);
+  GemmCfg pick_cfg(int dt, int np);
+};
+
+}  // namespace fm

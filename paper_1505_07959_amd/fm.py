@@ -1,0 +1,154 @@
+"""ctypes binding of libfm (include/fm.h): same names, argument marshalling only.
+
+Matrices are torch FP64 CUDA (HIP) tensors; the binding passes their device
+pointers and the current HIP stream.  Every computation runs in the library.
+Importing this module loads libfm.so and raises if it is missing.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfm.so")
+
+FM_OK = 0
+FM_WARN_NOT_CONVERGED = 1
+FM_ERR_INVALID = -1
+FM_ERR_NOMEM = -2
+FM_ERR_DEVICE = -3
+FM_ERR_NONFINITE = -4
+FM_ERR_UNSUPPORTED = -5
+
+FM_FLOW_INV_HOMOTOPY = 1
+FM_FLOW_INV_STEADY = 2
+FM_FLOW_SQRT_STEADY = 3
+
+FM_F64, FM_F32, FM_BF16, FM_F16 = 0, 1, 2, 3
+FM_COARSE_EULER, FM_COARSE_LEARNED = 0, 1
+
+DTYPES = {"f64": FM_F64, "f32": FM_F32, "bf16": FM_BF16, "f16": FM_F16}
+
+
+class FmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("libfm status %d: %s" % (status, msg))
+        self.status = status
+
+
+class fm_problem(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64)]
+
+
+class fm_params(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double), ("N", ctypes.c_int32), ("coarse_steps", ctypes.c_int32),
+                ("fine_steps", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("coarse", ctypes.c_int32),
+                ("max_refine", ctypes.c_int32), ("tol", ctypes.c_double), ("refine_tol", ctypes.c_double)]
+
+
+class fm_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("learned_slices", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("increment", ctypes.c_double), ("residual_before", ctypes.c_double),
+                ("residual", ctypes.c_double), ("hist", ctypes.c_double * 64)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "refine_steps": self.refine_steps, "learned_slices": self.learned_slices,
+                "status": self.status, "increment": self.increment, "residual_before": self.residual_before,
+                "residual": self.residual, "hist": list(self.hist[:max(0, min(self.iters, 64))])}
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError("libfm.so not found at %s; build it with `python -m paper_1505_07959_amd.build_lib`"
+                           % _LIB_PATH)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    lib.fm_flow_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(fm_problem), ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_char_p, P]
+    lib.fm_parareal_solve.argtypes = [P, PP, PP, ctypes.POINTER(fm_params), ctypes.POINTER(fm_stats), P]
+    lib.fm_fine_propagate.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, PP, PP, P]
+    lib.fm_coarse_propagate.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                        PP, PP, P]
+    lib.fm_destroy.argtypes = [P]
+    lib.fm_destroy.restype = None
+    lib.fm_last_error.restype = ctypes.c_char_p
+    for f in ("fm_flow_create", "fm_parareal_solve", "fm_fine_propagate", "fm_coarse_propagate"):
+        getattr(lib, f).restype = ctypes.c_int32
+    return lib
+
+
+lib = _load()
+
+
+def fm_last_error():
+    return lib.fm_last_error().decode()
+
+
+def _check(status):
+    if status < 0:
+        raise FmError(status, fm_last_error())
+    return status
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptrs(tensors):
+    if tensors is None:
+        return None
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        if t is None:
+            arr[i] = None
+            continue
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("matrices must be contiguous float64 device tensors")
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def fm_flow_create(problems, dtype, options=None, stream=None):
+    """problems: list of (kind, A) with A an n x n float64 device tensor.  Returns the handle."""
+    arr = (fm_problem * len(problems))()
+    for i, (kind, A) in enumerate(problems):
+        if A.dtype != torch.float64 or not A.is_cuda or A.dim() != 2 or A.stride(1) != 1:
+            raise ValueError("A must be a row-major float64 device matrix")
+        arr[i] = fm_problem(int(kind), 0, int(A.shape[0]), A.data_ptr(), int(A.stride(0)))
+    h = ctypes.c_void_p()
+    dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    _check(lib.fm_flow_create(ctypes.byref(h), arr, len(problems), dt,
+                              options.encode() if options else None, _stream(stream)))
+    return h
+
+
+def fm_parareal_solve(flow, X0, X_out, params, stream=None):
+    """params: list of dicts with the fm_params fields (one per problem).  Returns (status, stats list)."""
+    n = len(X_out)
+    prm = (fm_params * n)()
+    for i, p in enumerate(params):
+        prm[i] = fm_params(float(p["T"]), int(p["N"]), int(p.get("coarse_steps", 1)), int(p["fine_steps"]),
+                           int(p.get("max_iter", p["N"])), int(p.get("coarse", FM_COARSE_EULER)),
+                           int(p.get("max_refine", 0)), float(p.get("tol", 0.0)), float(p.get("refine_tol", 0.0)))
+    stats = (fm_stats * n)()
+    x0 = _ptrs(X0)
+    st = _check(lib.fm_parareal_solve(flow, x0, _ptrs(X_out), prm, stats, _stream(stream)))
+    return st, [s.as_dict() for s in stats]
+
+
+def fm_fine_propagate(flow, t_next, t_cur, steps, X_in, X_out, stream=None):
+    return _check(lib.fm_fine_propagate(flow, float(t_next), float(t_cur), int(steps), _ptrs(X_in), _ptrs(X_out),
+                                        _stream(stream)))
+
+
+def fm_coarse_propagate(flow, t_next, t_cur, steps, coarse, X_in, X_out, stream=None):
+    return _check(lib.fm_coarse_propagate(flow, float(t_next), float(t_cur), int(steps), int(coarse), _ptrs(X_in),
+                                          _ptrs(X_out), _stream(stream)))
+
+
+def fm_destroy(flow):
+    if flow is not None and flow.value:
+        lib.fm_destroy(flow)
