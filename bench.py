@@ -1,0 +1,176 @@
+"""Benchmark: parareal solves/s and fine-propagator MFMA TFLOP/s on one MI355X.
+
+Workload (one step = one whole parareal solve): inverse homotopy flow
+dX/dt = X (I - A) X, X(0) = I, T = 1, on the n = 4096 SPD matrix with
+lam ~ U[0.05, 4] (seed 2); N = 64 slices, one forward-Euler coarse step and
+16 RK4 fine steps per slice; all slice fine solves of an iteration batched in
+one grouped GEMM launch per product; FP64 correction; the solve stops when
+the increment max_n ||U^{k+1}_n - U^k_n||_F / ||U^{k+1}_n||_F <= 1e-8.
+Products run in FP32 on MFMA by default (--dtype f64 for the FP64 run).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.0, "f16": 2516.0}  # TFLOP/s, dense MFMA
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def traffic_for(kernel_key):
+    """HBM bytes per launch measured with rocprofv3 counters, if the kernel
+    source is unchanged since they were taken (else None)."""
+    try:
+        data = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    ent = data.get(kernel_key)
+    if not ent:
+        return None
+    src = open(os.path.join(ROOT, "paper_1505_07959_amd", "csrc", "gemm.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != ent.get("gemm_sha256"):
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(A, n, fine_steps_total, coarse_steps_total, sample_steps):
+    """Time the oracle's matrix RK4 step (numpy FP64) on a bounded sample and
+    scale to one solve of the same discrete method."""
+    import numpy as np
+    from oracle import MatrixAlgebra, HOMOTOPY, integrators
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    alg = MatrixAlgebra(n)
+    X = np.eye(n)
+    h = 1.0 / 1024
+    M = A - np.eye(n)
+    t0 = time.perf_counter()
+    for _ in range(sample_steps):
+        X = integrators.rk4_step(alg, HOMOTOPY, X, A, h, M)
+    t_step = (time.perf_counter() - t0) / sample_steps
+    # one Euler step = 2 of the 8 products of an RK4 step
+    t_solve = t_step * (fine_steps_total + 0.25 * coarse_steps_total)
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+            "sample": "%d RK4 steps of the n=%d matrix oracle (numpy FP64, %.2f s/step), scaled by the %d RK4 "
+                      "and %d Euler steps of one GPU solve" % (sample_steps, n, t_step, fine_steps_total,
+                                                              coarse_steps_total)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16", "f16"])
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--slices", type=int, default=64)
+    ap.add_argument("--fine-steps", type=int, default=16)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--max-iter", type=int, default=64)
+    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (time slices would shard over "
+              "GPUs as described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1505_07959_amd import fm, inputs
+
+    n, N, S = args.n, args.slices, args.fine_steps
+    log("building input n=%d" % n)
+    A, Q, lam = inputs.large_problem(n)
+    Ad = torch.from_numpy(A).cuda()
+    out = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    prm = {"T": 1.0, "N": N, "coarse_steps": 1, "fine_steps": S, "max_iter": args.max_iter, "tol": args.tol,
+           "coarse": fm.FM_COARSE_EULER, "max_refine": 0}
+    h = fm.fm_flow_create([(fm.FM_FLOW_INV_HOMOTOPY, Ad)], args.dtype, "timing=1")
+    stream = torch.cuda.current_stream()
+
+    def one():
+        st, stats = fm.fm_parareal_solve(h, None, [out], [prm], stream=stream)
+        return st, stats[0]
+
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        st, s = one()
+        log("warmup %d: %.2f s, iters %d, status %d" % (w, time.perf_counter() - t, s["iters"], st))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        st, s = one()
+        stats.append(s)
+        log("step %d: iters %d, increment %.3e, status %d" % (k, s["iters"], s["increment"], st))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fm.fm_destroy(h)
+
+    s = stats[-1]
+    converged = all(x["status"] == 0 for x in stats)
+    solves_per_s = args.steps / elapsed if converged else 0.0
+    avg_launch_ms = s["fine_ms"] / max(1, s["fine_launches"])
+    flops_per_launch = s["fine_flops"] / max(1, s["fine_launches"])
+    achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    iters = s["iters"]
+    fine_steps_total = sum(N - k for k in range(iters)) * S
+    coarse_steps_total = N + sum(N - k - 1 for k in range(iters))
+    total_fine_flops = fine_steps_total * 16.0 * n ** 3
+    log("iters %d  hist %s" % (iters, ["%.1e" % x for x in s["hist"]]))
+    log("fine RK4-epilogue GEMM: %d launches, avg %.3f ms, %.1f TFLOP/s; fine phases %.2f s of %.2f s/solve" %
+        (s["fine_launches"], avg_launch_ms, achieved, s["fine_phase_ms"] / 1e3, elapsed / args.steps))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (%d oracle RK4 steps at n=%d)" % (args.cpu_sample_steps, n))
+        cpu = cpu_baseline(A, n, fine_steps_total, coarse_steps_total, args.cpu_sample_steps)
+
+    key = "gemm_%s_rk4_n%d" % (args.dtype, n)
+    res = {
+        "metric": "parareal solves/s + MFMA TFLOP/s at 1e-8 rel err; learned vs Euler coarse",
+        "value": solves_per_s,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "inverse homotopy dX/dt=X(I-A)X, n=%d SPD lam~U[0.05,4] seed 2, N=%d slices, "
+                               "RK4 %d steps/slice, Euler 1 step/slice, %s MFMA products, FP64 state+correction, "
+                               "stop at increment <= %g" % (n, N, S, args.dtype, args.tol),
+                   "n": n, "slices": N, "fine_steps": S, "coarse_steps": 1, "tol": args.tol,
+                   "iterations": iters, "converged": converged,
+                   "fine_tflops_whole_solve": total_fine_flops / (elapsed / args.steps) / 1e12},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.dtype], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK[args.dtype], "traffic": traffic_for(key),
+                     "kernel": "gemm_kernel RK4-epilogue (fine propagator), avg of %d launches, %.3e flop/launch"
+                               % (s["fine_launches"], flops_per_launch)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -112,6 +112,14 @@ typedef struct {
                               ||I - A X||_F / sqrt(n) or ||A - X^2||_F / ||A||_F */
   double residual;         /* the same after refinement */
   double hist[64];         /* increment of iterations 1..64 */
+  /* Filled when the flow was created with option "timing=1" (else 0): HIP
+   * event timing, on the solve's stream, of every launch of the fine
+   * propagator's second product of an RK4 stage (the RK4-epilogue GEMM).   */
+  int32_t fine_launches;   /* number of such launches */
+  int32_t reserved_;
+  double fine_ms;          /* their summed duration, milliseconds */
+  double fine_flops;       /* their algorithmic flops: 2 n^3 per problem-slice */
+  double fine_phase_ms;    /* duration of the whole batched fine phases */
 } fm_stats;
 
 /*
@@ -120,7 +128,8 @@ typedef struct {
  * dtype copies); allocates the parareal workspace lazily in the first solve.
  * options: NULL or "key=value;key=value": coarse_model=<path> loads learned
  * coarse weights (file written by the training script), autotune=0|1 (default
- * 1: time candidate tile shapes on first use), autotune_cache=<path>.
+ * 1: time candidate tile shapes on first use), autotune_cache=<path>,
+ * timing=0|1 (default 0: fill the timing fields of fm_stats).
  * out: host; receives the handle.  Returns FM_ERR_INVALID for batch < 1,
  * n out of range, lda < n, an unknown kind/dtype or a NULL A.
  */

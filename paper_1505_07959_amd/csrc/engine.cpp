@@ -103,7 +103,36 @@ fm_status Flow::reserve_ring(size_t bytes, hipStream_t st) {
   return FM_OK;
 }
 
+hipEvent_t Flow::next_event() {
+  if (ev_used == ev.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ev.push_back(e);
+  }
+  return ev[ev_used++];
+}
+
+fm_status Flow::collect_timing() {
+  for (auto& pr : ev_pairs) {
+    float ms = 0.f;
+    FM_HIP(hipEventElapsedTime(&ms, ev[pr.first], ev[pr.first + 1]));
+    t_ms += ms;
+    t_flops += pr.second;
+    t_launches++;
+  }
+  for (int i : phase_pairs) {
+    float ms = 0.f;
+    FM_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+    t_phase_ms += ms;
+  }
+  ev_pairs.clear();
+  phase_pairs.clear();
+  ev_used = 0;
+  return FM_OK;
+}
+
 Flow::~Flow() {
+  for (auto e : ev) (void)hipEventDestroy(e);
   for (auto& in : inst) {
     if (in.A64) (void)hipFree(in.A64);
     if (in.Bop) (void)hipFree(in.Bop);
@@ -169,6 +198,7 @@ fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char*
   parse_options(options, kv);
   if (kv.count("autotune")) autotune = kv["autotune"] != "0";
   if (kv.count("autotune_cache")) autotune_cache = kv["autotune_cache"];
+  if (kv.count("timing")) timing = kv["timing"] != "0";
   FM_TRY(ring.init(size_t(256) << 20));
   inst.resize(nb);
   for (int i = 0; i < nb; ++i) {
@@ -302,6 +332,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
     const int* ts;
     int n;
     int total;
+    double flops;  // algorithmic: 2 n^3 per item (unpadded order)
   };
   std::vector<Launch> seq;
   {
@@ -327,11 +358,13 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
       std::vector<GItem> sub;
       std::vector<int> ts(1, 0);
       int total = 0;
+      L.flops = 0;
       for (int j : g.second) {
         sub.push_back(items[j]);
         const int tpn = items[j].np / L.cfg.bm;
         total += tpn * tpn;
         ts.push_back(total);
+        L.flops += 2.0 * (double)items[j].n * items[j].n * items[j].n;
       }
       void* di = nullptr;
       void* dts = nullptr;
@@ -349,10 +382,34 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
     FM_TRY(prepare(l1[s], i1[s], EPI_AFFINE));
     FM_TRY(prepare(l2[s], i2[s], EPI_RK4));
   }
+  int phase_ev = -1;
+  if (timing) {
+    phase_ev = (int)ev_used;
+    hipEvent_t e0 = next_event(), e1 = next_event();
+    if (!e0 || !e1) timing = false;
+    else FM_HIP(hipEventRecord(e0, st));
+  }
   for (int step = 0; step < steps; ++step)
-    for (const Launch& L : seq)
+    for (const Launch& L : seq) {
+      const bool rec = timing && L.epi == EPI_RK4;
+      int idx = -1;
+      if (rec) {
+        idx = (int)ev_used;
+        hipEvent_t a = next_event(), b = next_event();
+        if (a && b) FM_HIP(hipEventRecord(a, st));
+        else idx = -1;
+      }
       FM_HIP(launch_gemm(L.cfg, L.epi, L.items, L.ts, L.n, L.total, std::min(L.total, gemm_max_grid(L.cfg)),
                          nullptr, st));
+      if (idx >= 0) {
+        FM_HIP(hipEventRecord(ev[idx + 1], st));
+        ev_pairs.push_back({idx, L.flops});
+      }
+    }
+  if (timing && phase_ev >= 0) {
+    FM_HIP(hipEventRecord(ev[phase_ev + 1], st));
+    phase_pairs.push_back(phase_ev);
+  }
   return FM_OK;
 }
 
@@ -630,6 +687,11 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
   }
   FM_HIP(hipStreamSynchronize(st));
   ring.reset();
+  t_launches = 0;
+  t_ms = t_flops = t_phase_ms = 0;
+  ev_pairs.clear();
+  phase_pairs.clear();
+  ev_used = 0;
 
   // learned coefficient tables (one network evaluation per slice substep)
   for (int i = 0; i < batch; ++i) {
@@ -765,6 +827,7 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
     FM_HIP(launch_reduce_pairs(part, (int)npairs, nblk, d_red, st));
     FM_HIP(hipMemcpyAsync(hredu, d_red, npairs * 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     FM_HIP(hipStreamSynchronize(st));
+    if (timing) FM_TRY(collect_timing());
     for (int i = 0; i < batch; ++i) {
       if (!live[i]) continue;
       double inc = 0.0;
@@ -809,6 +872,10 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
       stats[i].increment = lastinc[i];
       for (size_t j = 0; j < hist[i].size() && j < 64; ++j) stats[i].hist[j] = hist[i][j];
       stats[i].residual_before = stats[i].residual = NAN;
+      stats[i].fine_launches = (int32_t)t_launches;
+      stats[i].fine_ms = t_ms;
+      stats[i].fine_flops = t_flops;
+      stats[i].fine_phase_ms = t_phase_ms;
     }
   }
   FM_TRY(refine(which, X, prm, stats, st));

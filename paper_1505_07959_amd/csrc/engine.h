@@ -119,6 +119,17 @@ struct Flow {
   double* hredu = nullptr;  // pinned host copy of reduced triples
   size_t hredu_cap = 0;
 
+  // optional HIP-event timing of the fine propagator (option timing=1)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;      // event pool
+  size_t ev_used = 0;
+  std::vector<std::pair<int, double>> ev_pairs;  // (index of start event, flops) of RK4-epilogue launches
+  std::vector<int> phase_pairs;    // start-event index of each fine phase
+  int64_t t_launches = 0;
+  double t_ms = 0, t_flops = 0, t_phase_ms = 0;
+  hipEvent_t next_event();
+  fm_status collect_timing();      // after a synchronisation: fold recorded pairs into the totals
+
   ~Flow();
   fm_status init(const fm_problem* p, int32_t batch, int32_t dtype, const char* options, hipStream_t st);
 

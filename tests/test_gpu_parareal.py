@@ -73,9 +73,9 @@ def test_small_workload_golden_and_lu():
 
 def test_tolerance_stop_matches_oracle():
     A, Q, lam = inputs.small_problem()
-    ref = _oracle_parareal(MatrixAlgebra(64), HOMOTOPY, A, np.eye(64), 1.0, 8, 32, 1, 8, 1e-6)
-    st, stats, X = _solve(A, HOMOTOPY, "f64", {"T": 1.0, "N": 8, "fine_steps": 32, "max_iter": 8, "tol": 1e-6})
-    assert stats["iters"] == ref["iters"] < 8
+    ref = _oracle_parareal(MatrixAlgebra(64), HOMOTOPY, A, np.eye(64), 1.0, 8, 32, 1, 8, 1e-5)
+    st, stats, X = _solve(A, HOMOTOPY, "f64", {"T": 1.0, "N": 8, "fine_steps": 32, "max_iter": 8, "tol": 1e-5})
+    assert stats["iters"] == ref["iters"] == 7
     assert rel(X, ref["U"][-1]) <= 1e-10
 
 
