@@ -102,7 +102,7 @@ def main():
     out = torch.empty((n, n), dtype=torch.float64, device="cuda")
     prm = {"T": 1.0, "N": N, "coarse_steps": 1, "fine_steps": S, "max_iter": args.max_iter, "tol": args.tol,
            "coarse": fm.FM_COARSE_EULER, "max_refine": 0}
-    h = fm.fm_flow_create([(fm.FM_FLOW_INV_HOMOTOPY, Ad)], args.dtype, "timing=1")
+    h = fm.fm_flow_create([(fm.FM_FLOW_INV_HOMOTOPY, Ad)], args.dtype, "timing=1;verbose=1")
     stream = torch.cuda.current_stream()
 
     def one():

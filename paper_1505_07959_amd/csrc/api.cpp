@@ -160,3 +160,101 @@ void fm_destroy(fm_flow f) {
 const char* fm_last_error(void) { return fm::last_error(); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- training
+#include "fm_mlp.h"
+#include "fm_train.h"
+
+extern "C" {
+
+int32_t fm_mlp_param_count(void) { return fm::mlp_param_count(); }
+
+static fm_status launch_result(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fm::hip_status(e, what);
+  return FM_OK;
+}
+
+fm_status fm_mlp_forward(const float* theta, const float* norm, const float* X, int64_t S, float* Y, float* acts,
+                         void* hip_stream) {
+  fm::clear_error();
+  if (!theta || !norm || !X || !Y || S < 0) {
+    set_error("fm_mlp_forward: NULL pointer or negative size");
+    return FM_ERR_INVALID;
+  }
+  return launch_result(fm::mlp_forward(theta, norm, X, S, Y, acts, (hipStream_t)hip_stream), "mlp forward");
+}
+
+fm_status fm_mlp_loss(const float* Y, const float* cbase, const double* G, const double* bD, const double* fD,
+                      const double* fn, float rho, int64_t S, float* dY, double* Ls, double* Lsum,
+                      void* hip_stream) {
+  fm::clear_error();
+  if (!Y || !cbase || !G || !bD || !fD || !fn || !dY || !Ls || S < 0) {
+    set_error("fm_mlp_loss: NULL pointer or negative size");
+    return FM_ERR_INVALID;
+  }
+  return launch_result(fm::mlp_loss(Y, cbase, G, bD, fD, fn, rho, S, dY, Ls, Lsum, (hipStream_t)hip_stream),
+                       "mlp loss");
+}
+
+fm_status fm_mlp_backward(const float* theta, const float* norm, const float* X, const float* acts,
+                          const float* dY, int64_t S, float* deltas, float* grad, void* hip_stream) {
+  fm::clear_error();
+  if (!theta || !norm || !X || !acts || !dY || !deltas || !grad || S < 0) {
+    set_error("fm_mlp_backward: NULL pointer or negative size");
+    return FM_ERR_INVALID;
+  }
+  return launch_result(fm::mlp_backward(theta, norm, X, acts, dY, S, deltas, grad, (hipStream_t)hip_stream),
+                       "mlp backward");
+}
+
+fm_status fm_mlp_adam(float* theta, const float* grad, float* m, float* v, int64_t count, int32_t t, float lr,
+                      void* hip_stream) {
+  fm::clear_error();
+  if (!theta || !grad || !m || !v || count < 0 || t < 1) {
+    set_error("fm_mlp_adam: NULL pointer, negative size or t < 1");
+    return FM_ERR_INVALID;
+  }
+  return launch_result(fm::mlp_adam(theta, grad, m, v, count, t, lr, 0.9f, 0.999f, 1e-8f, (hipStream_t)hip_stream),
+                       "adam");
+}
+
+fm_status fm_learned_features(fm_flow f, double h, const double* const* X, const double* const* FX, double* G,
+                              double* bD, double* fD, double* fn, int64_t row0, void* hip_stream) {
+  fm::clear_error();
+  fm_status s = check_flow(f);
+  if (s != FM_OK) return s;
+  if ((s = check_ptrs(f, (const void* const*)X, "X")) != FM_OK) return s;
+  if ((s = check_ptrs(f, (const void* const*)FX, "FX")) != FM_OK) return s;
+  if (!G || !bD || !fD || !fn || row0 < 0 || !std::isfinite(h)) {
+    set_error("fm_learned_features: NULL output, negative row0 or non-finite h");
+    return FM_ERR_INVALID;
+  }
+  return f->impl.features(h, X, FX, G, bD, fD, fn, row0, (hipStream_t)hip_stream);
+}
+
+fm_status fm_trace_moments(fm_flow f, double* mu_host, void* hip_stream) {
+  fm::clear_error();
+  fm_status s = check_flow(f);
+  if (s != FM_OK) return s;
+  if (!mu_host) {
+    set_error("mu_host is NULL");
+    return FM_ERR_INVALID;
+  }
+  if ((s = f->impl.ensure_moments((hipStream_t)hip_stream)) != FM_OK) return s;
+  for (int i = 0; i < f->impl.batch; ++i)
+    for (int q = 0; q < 4; ++q) mu_host[i * 4 + q] = f->impl.inst[i].mu[q];
+  return FM_OK;
+}
+
+fm_status fm_flow_set_coarse_model(fm_flow f, int32_t kind, const double* theta_host, const double* norm_host) {
+  fm::clear_error();
+  fm_status s = check_flow(f);
+  if (s != FM_OK) return s;
+  if (!theta_host || !norm_host || (kind != FM_FLOW_INV_HOMOTOPY && kind != FM_FLOW_INV_STEADY)) {
+    set_error("fm_flow_set_coarse_model: NULL weights or a kind without learned step");
+    return FM_ERR_INVALID;
+  }
+  return f->impl.set_model(kind, theta_host, norm_host);
+}
+
+}  // extern "C"

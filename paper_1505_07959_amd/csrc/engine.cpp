@@ -3,12 +3,14 @@
 // stream; the only host synchronisation is one small read per parareal
 // iteration (the increment) and per refinement step (the residual).
 #include "engine.h"
+#include "fm_mlp.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <chrono>
 #include <map>
 
 namespace fm {
@@ -133,6 +135,8 @@ fm_status Flow::collect_timing() {
 
 Flow::~Flow() {
   for (auto e : ev) (void)hipEventDestroy(e);
+  if (model.d_theta) (void)hipFree(model.d_theta);
+  if (model.d_norm) (void)hipFree(model.d_norm);
   for (auto& in : inst) {
     if (in.A64) (void)hipFree(in.A64);
     if (in.Bop) (void)hipFree(in.Bop);
@@ -199,6 +203,7 @@ fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char*
   if (kv.count("autotune")) autotune = kv["autotune"] != "0";
   if (kv.count("autotune_cache")) autotune_cache = kv["autotune_cache"];
   if (kv.count("timing")) timing = kv["timing"] != "0";
+  if (kv.count("verbose")) verbose = kv["verbose"] != "0";
   FM_TRY(ring.init(size_t(256) << 20));
   inst.resize(nb);
   for (int i = 0; i < nb; ++i) {
@@ -615,10 +620,12 @@ fm_status Flow::coarse_propagate(double t1, double t0, int steps, int coarse, co
     }
     if (pass == 0) FM_TRY(prop.reserve(prop.used));
   }
-  if (coarse == FM_COARSE_LEARNED)
+  if (coarse == FM_COARSE_LEARNED) {
+    std::vector<CoefRow> rows;
     for (int i = 0; i < batch; ++i)
-      for (int j = 0; j < steps; ++j)
-        FM_TRY(learned_coeffs(i, t0 + j * slots[i].h, slots[i].h, coefs.data() + ((size_t)i * steps + j) * 8));
+      for (int j = 0; j < steps; ++j) rows.push_back(CoefRow{i, t0 + j * slots[i].h, slots[i].h});
+    FM_TRY(learned_table(rows, coefs.data(), st));
+  }
   ring.reset();
   FM_HIP(hipStreamSynchronize(st));
   for (int i = 0; i < batch; ++i) FM_HIP(copy_in(slots[i].xout, inst[i].np, xin[i], inst[i].n, st));
@@ -649,6 +656,8 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
     // learned: coarse choice per slice and coefficient table
     std::vector<double> coef;    // N * coarse_steps * 8
     std::vector<int> use_learned;
+    std::vector<void*> lk2, lk3;  // per-slice scratch of the candidate steps
+    std::vector<double*> gl;      // per-slice learned candidate G_L(U^k_n)
   };
   std::vector<IW> w(batch);
   for (int pass = 0; pass < 2; ++pass) {
@@ -682,10 +691,20 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
       q.ck1 = lrn ? work.take(np2 * e) : nullptr;
       q.ck2 = lrn ? work.take(np2 * e) : nullptr;
       q.ck3 = lrn ? work.take(np2 * e) : nullptr;
+      q.lk2.assign(N, nullptr);
+      q.lk3.assign(N, nullptr);
+      q.gl.assign(N, nullptr);
+      if (lrn)
+        for (int s = 0; s < N; ++s) {
+          q.lk2[s] = work.take(np2 * e);
+          q.lk3[s] = work.take(np2 * e);
+          q.gl[s] = (double*)work.take(np2 * 8);
+        }
     }
     if (pass == 0) FM_TRY(work.reserve(work.used));
   }
   FM_HIP(hipStreamSynchronize(st));
+  const auto t_start = std::chrono::steady_clock::now();
   ring.reset();
   t_launches = 0;
   t_ms = t_flops = t_phase_ms = 0;
@@ -693,16 +712,28 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
   phase_pairs.clear();
   ev_used = 0;
 
-  // learned coefficient tables (one network evaluation per slice substep)
-  for (int i = 0; i < batch; ++i) {
-    if (prm[i].coarse != FM_COARSE_LEARNED) continue;
-    const int N = prm[i].N, C = prm[i].coarse_steps;
-    w[i].coef.resize((size_t)N * C * 8);
-    w[i].use_learned.assign(N, 1);
-    for (int s = 0; s < N; ++s) {
-      const double ta = s * prm[i].T / N, tb = (s + 1) * prm[i].T / N;
-      const double h = (tb - ta) / C;
-      for (int j = 0; j < C; ++j) FM_TRY(learned_coeffs(i, ta + j * h, h, &w[i].coef[((size_t)s * C + j) * 8]));
+  // learned coefficient tables: one batched network evaluation for every
+  // (problem, slice, substep); inputs (t, h, mu_1..4)
+  {
+    std::vector<CoefRow> rows;
+    for (int i = 0; i < batch; ++i) {
+      if (prm[i].coarse != FM_COARSE_LEARNED) continue;
+      const int N = prm[i].N, C = prm[i].coarse_steps;
+      w[i].use_learned.assign(N, 1);
+      for (int s = 0; s < N; ++s) {
+        const double ta = s * prm[i].T / N, tb = (s + 1) * prm[i].T / N;
+        const double h = (tb - ta) / C;
+        for (int j = 0; j < C; ++j) rows.push_back(CoefRow{i, ta + j * h, h});
+      }
+    }
+    std::vector<double> table(rows.size() * 8);
+    FM_TRY(learned_table(rows, table.data(), st));
+    size_t r = 0;
+    for (int i = 0; i < batch; ++i) {
+      if (prm[i].coarse != FM_COARSE_LEARNED) continue;
+      const size_t cnt = (size_t)prm[i].N * prm[i].coarse_steps;
+      w[i].coef.assign(table.begin() + r * 8, table.begin() + (r + cnt) * 8);
+      r += cnt;
     }
   }
 
@@ -745,21 +776,79 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
     for (int i = 0; i < batch; ++i)
       if (s < prm[i].N) FM_HIP(copy_f64(w[i].U[s + 1], w[i].Go[s], (int64_t)inst[i].np * inst[i].np, st));
   }
+  const size_t npairs = (size_t)Nmax * batch;
+  if (any_learned) {
+    // Step 0 keeps the learned value unless it is not finite: find the first
+    // non-finite slice of each learned problem and redo the sweep from there
+    // with Euler on that slice (rare path, one check per redone slice).
+    FM_TRY(ensure_hredu(npairs * 3));
+    double* sums = nullptr;
+    double* dpart = nullptr;
+    for (int pass = 0; pass < 2; ++pass) {
+      prop.measuring = (pass == 0);
+      prop.used = 0;
+      sums = (double*)prop.take(npairs * 8);
+      dpart = (double*)prop.take(npairs * 16 * 8);
+      if (pass == 0) {
+        FM_HIP(hipStreamSynchronize(st));
+        FM_TRY(prop.reserve(prop.used));
+      }
+    }
+    auto norms = [&](const std::vector<std::pair<int, int>>& is) -> fm_status {
+      std::vector<DotItem> it;
+      for (auto& q : is) {
+        const int i = q.first, t = q.second;
+        it.push_back(DotItem{w[i].Go[t], w[i].Go[t], (int64_t)inst[i].np * inst[i].np, t * batch + i, 0, nullptr});
+      }
+      if (it.empty()) return FM_OK;
+      void* d = nullptr;
+      FM_TRY(push(it.data(), it.size() * sizeof(DotItem), &d, st));
+      FM_HIP(launch_dots((const DotItem*)d, (int)it.size(), dpart, 16, sums, st));
+      FM_HIP(hipMemcpyAsync(hredu, sums, npairs * sizeof(double), hipMemcpyDeviceToHost, st));
+      FM_HIP(hipStreamSynchronize(st));
+      ring.reset();
+      return FM_OK;
+    };
+    std::vector<std::pair<int, int>> all;
+    for (int i = 0; i < batch; ++i)
+      if (prm[i].coarse == FM_COARSE_LEARNED)
+        for (int t = 0; t < prm[i].N; ++t) all.push_back({i, t});
+    FM_TRY(norms(all));
+    for (int i = 0; i < batch; ++i) {
+      if (prm[i].coarse != FM_COARSE_LEARNED) continue;
+      int first_bad = -1;
+      for (int t = 0; t < prm[i].N && first_bad < 0; ++t)
+        if (!std::isfinite(hredu[(size_t)t * batch + i])) first_bad = t;
+      if (first_bad < 0) continue;
+      for (int t = first_bad; t < prm[i].N; ++t) {
+        std::vector<CoarseSlot> one(1, coarse_slot(i, t, w[i].U[t], w[i].Go[t], true));
+        FM_TRY(run_coarse(one, prm[i].coarse_steps, st));
+        FM_TRY(norms({{i, t}}));
+        if (!std::isfinite(hredu[(size_t)t * batch + i])) {
+          w[i].use_learned[t] = 0;
+          one[0] = coarse_slot(i, t, w[i].U[t], w[i].Go[t], false);
+          FM_TRY(run_coarse(one, prm[i].coarse_steps, st));
+        }
+        FM_HIP(copy_f64(w[i].U[t + 1], w[i].Go[t], (int64_t)inst[i].np * inst[i].np, st));
+      }
+    }
+  }
 
   // ---- iterations
   std::vector<int> live(batch, 0), iters(batch, 0);
   std::vector<fm_status> ist(batch, FM_OK);
   std::vector<double> lastinc(batch, 0.0);
   std::vector<std::vector<double>> hist(batch);
+  std::vector<int> learned_count(batch, 0);
   for (int i = 0; i < batch; ++i) live[i] = prm[i].max_iter > 0 && prm[i].N > 0;
   int nblk = 1;
   for (int i = 0; i < batch; ++i) {
     int64_t np2 = (int64_t)inst[i].np * inst[i].np;
     nblk = std::max<int>(nblk, (int)std::min<int64_t>(256, (np2 + 4095) / 4096));
   }
-  const size_t npairs = (size_t)Nmax * batch;
-  FM_TRY(ensure_part(npairs * nblk * 3 + npairs * 3));
+  FM_TRY(ensure_part(npairs * nblk * 3 + npairs * 3 + npairs * 2));
   double* d_red = part + npairs * nblk * 3;
+  double* d_cand = d_red + npairs * 3;  // defects of the learned / Euler candidates
   FM_TRY(ensure_hredu(npairs * 3));
 
   for (int k = 0;; ++k) {
@@ -792,11 +881,56 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
       for (auto& g : by) FM_TRY(run_fine(g.second, g.first, st));
     }
     // learned coarse: choose per slice between the learned and the Euler step
-    // by their defect against F(U^k_n) (fallback), and recompute G_old with
-    // the chosen step.
-    for (int i = 0; i < batch; ++i) {
-      if (!live[i] || prm[i].coarse != FM_COARSE_LEARNED) continue;
-      // handled below (needs device defects): see learned_fallback
+    // by their defect against F(U^k_n) (the Euler fallback), and set G_old to
+    // the chosen step at U^k_n.  Candidates of all slices run in parallel on
+    // the slices' own scratch.
+    {
+      std::vector<CoarseSlot> ce, cl;
+      std::vector<std::pair<int, int>> cl_is;  // (problem, slice) of each candidate
+      std::vector<DotItem> di;
+      for (int s = k; s < Nmax; ++s)
+        for (int i = 0; i < batch; ++i) {
+          if (!live[i] || s >= prm[i].N || prm[i].coarse != FM_COARSE_LEARNED) continue;
+          CoarseSlot c = coarse_slot(i, s, w[i].U[s], w[i].Go[s], false);
+          c.y0 = w[i].ya[s];
+          c.y1 = w[i].yb[s];
+          c.p = w[i].p[s];
+          c.k1 = w[i].kacc[s];
+          c.k2 = w[i].lk2[s];
+          c.k3 = w[i].lk3[s];
+          ce.push_back(c);
+          c.learned = 1;
+          c.xout = w[i].gl[s];
+          c.coef = &w[i].coef[(size_t)s * prm[i].coarse_steps * 8];
+          cl.push_back(c);
+          cl_is.push_back({i, s});
+          const int64_t cnt = (int64_t)inst[i].np * inst[i].np;
+          di.push_back(DotItem{w[i].gl[s], w[i].gl[s], cnt, (int)(s * batch + i), 0, w[i].Fo[s]});
+          di.push_back(DotItem{w[i].Go[s], w[i].Go[s], cnt, (int)(npairs + s * batch + i), 0, w[i].Fo[s]});
+        }
+      if (!ce.empty()) {
+        FM_TRY(run_coarse_mixed(ce));
+        FM_TRY(run_coarse_mixed(cl));
+        void* d = nullptr;
+        FM_TRY(push(di.data(), di.size() * sizeof(DotItem), &d, st));
+        FM_HIP(launch_dots((const DotItem*)d, (int)di.size(), part, 16, d_cand, st));
+        FM_HIP(hipMemcpyAsync(hredu, d_cand, npairs * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        FM_HIP(hipStreamSynchronize(st));
+        ring.reset();
+        for (const auto& q : cl_is) {
+          const int i = q.first, s2 = q.second;
+          const double dl = hredu[(size_t)s2 * batch + i], de = hredu[npairs + (size_t)s2 * batch + i];
+          w[i].use_learned[s2] = (std::isfinite(dl) && dl <= de) ? 1 : 0;
+          if (w[i].use_learned[s2])
+            FM_HIP(copy_f64(w[i].Go[s2], w[i].gl[s2], (int64_t)inst[i].np * inst[i].np, st));
+        }
+        for (int i = 0; i < batch; ++i)
+          if (live[i] && prm[i].coarse == FM_COARSE_LEARNED) {
+            int c2 = 0;
+            for (int s2 = k; s2 < prm[i].N; ++s2) c2 += w[i].use_learned[s2];
+            learned_count[i] = c2;
+          }
+      }
     }
     // sequential correction sweep
     for (int s = k; s < Nmax; ++s) {
@@ -856,6 +990,18 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
         ist[i] = FM_WARN_NOT_CONVERGED;
       }
     }
+    if (verbose) {
+      double worst = 0.0;
+      int nlive = 0;
+      for (int i = 0; i < batch; ++i) {
+        if (iters[i] == k + 1) worst = std::max(worst, lastinc[i]);
+        nlive += live[i];
+      }
+      const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+      fprintf(stderr, "[fm] iteration %d: max increment %.3e, %d problems still iterating, %.2f s\n", k + 1, worst,
+              nlive, sec);
+      fflush(stderr);
+    }
   }
 
   // ---- result, residual and refinement
@@ -872,6 +1018,7 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
       stats[i].increment = lastinc[i];
       for (size_t j = 0; j < hist[i].size() && j < 64; ++j) stats[i].hist[j] = hist[i][j];
       stats[i].residual_before = stats[i].residual = NAN;
+      stats[i].learned_slices = learned_count[i];
       stats[i].fine_launches = (int32_t)t_launches;
       stats[i].fine_ms = t_ms;
       stats[i].fine_flops = t_flops;
@@ -892,14 +1039,23 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
 }
 
 // ----------------------------------------------------------- refinement
-// Inverse flows: R = I - A X, X <- X + X R (Newton-Schulz).  Square root:
-// R = A - X^2, X <- X + H with X H + H X = R solved by conjugate gradients.
-// The residual ||R||_F / ||target scale|| is computed before every step.
+// Inverse flows: R = I - A X, X <- X + X R (Newton-Schulz, I - A X+ = R^2).
+// Square root: R = A - X^2, X <- X + H with X H + H X = R (full Newton step),
+// H by conjugate gradients on the operator H -> X H + H X, which is symmetric
+// positive definite in the Frobenius inner product for symmetric positive
+// definite X; two FP64 products per CG iteration.  All problems of the batch
+// advance together; the relative residual (||R||_F / sqrt(n) for the inverse,
+// ||R||_F / ||A||_F for the root) is read back once per refinement step.
+static constexpr int REF_DOT_BLOCKS = 32;
+
 fm_status Flow::refine(const std::vector<int>& which, std::vector<double*>& X, const fm_params* prm,
                        fm_stats* stats, hipStream_t st) {
   if (which.empty()) return FM_OK;
-  // scratch: R and X2 per problem (FP64)
-  std::vector<double*> R(batch, nullptr), X2(batch, nullptr);
+  std::vector<double*> R(batch, nullptr), X2(batch, nullptr), H(batch, nullptr), r(batch, nullptr),
+      p(batch, nullptr), Ap(batch, nullptr), T(batch, nullptr);
+  double *sc = nullptr, *dpart = nullptr;
+  bool any_sqrt = false;
+  for (int i : which) any_sqrt |= inst[i].kind == FM_FLOW_SQRT_STEADY;
   for (int pass = 0; pass < 2; ++pass) {
     prop.measuring = (pass == 0);
     prop.used = 0;
@@ -907,29 +1063,66 @@ fm_status Flow::refine(const std::vector<int>& which, std::vector<double*>& X, c
       const size_t np2 = (size_t)inst[i].np * inst[i].np;
       R[i] = (double*)prop.take(np2 * 8);
       X2[i] = (double*)prop.take(np2 * 8);
+      if (inst[i].kind == FM_FLOW_SQRT_STEADY) {
+        H[i] = (double*)prop.take(np2 * 8);
+        r[i] = (double*)prop.take(np2 * 8);
+        p[i] = (double*)prop.take(np2 * 8);
+        Ap[i] = (double*)prop.take(np2 * 8);
+        T[i] = (double*)prop.take(np2 * 8);
+      }
     }
+    sc = (double*)prop.take((size_t)batch * 6 * 8);  // nrm | rrA | rrB | pap | rr0 | spare
+    dpart = (double*)prop.take((size_t)batch * REF_DOT_BLOCKS * 8);
     if (pass == 0) {
       FM_HIP(hipStreamSynchronize(st));
       FM_TRY(prop.reserve(prop.used));
     }
   }
-  FM_TRY(ensure_part(4096 + 2 * batch));
-  FM_TRY(ensure_hredu(2 * batch + 2));
-  std::vector<int> active = which;
-  std::vector<int> steps(batch, 0);
-  std::vector<double> scale(batch, 1.0);
-  // ||A||_F for the square-root residual
-  for (int i : which)
-    if (inst[i].kind == FM_FLOW_SQRT_STEADY) {
-      FM_HIP(launch_dot(inst[i].A64, inst[i].A64, (int64_t)inst[i].np * inst[i].np, part, 64, part + 4096 + i, st));
+  double* nrm = sc;
+  double* rrA = sc + batch;
+  double* rrB = sc + 2 * batch;
+  double* pap = sc + 3 * batch;
+  FM_TRY(ensure_hredu((size_t)batch * 2 + 2));
+
+  auto dots = [&](const std::vector<int>& ids, const std::vector<const double*>& a,
+                  const std::vector<const double*>& b, double* out) -> fm_status {
+    std::vector<DotItem> it;
+    for (size_t j = 0; j < ids.size(); ++j) {
+      const int i = ids[j];
+      it.push_back(DotItem{a[j], b[j], (int64_t)inst[i].np * inst[i].np, i, 0, nullptr});
     }
-  FM_HIP(hipMemcpyAsync(hredu, part + 4096, batch * sizeof(double), hipMemcpyDeviceToHost, st));
-  FM_HIP(hipStreamSynchronize(st));
-  for (int i : which) scale[i] = inst[i].kind == FM_FLOW_SQRT_STEADY ? std::sqrt(hredu[i]) : std::sqrt((double)inst[i].n);
-  bool first = true;
-  while (!active.empty()) {
+    if (it.empty()) return FM_OK;
+    void* d = nullptr;
+    FM_TRY(push(it.data(), it.size() * sizeof(DotItem), &d, st));
+    FM_HIP(launch_dots((const DotItem*)d, (int)it.size(), dpart, REF_DOT_BLOCKS, out, st));
+    return FM_OK;
+  };
+  auto fetch = [&](const double* d) -> fm_status {
+    FM_HIP(hipMemcpyAsync(hredu, d, batch * sizeof(double), hipMemcpyDeviceToHost, st));
     FM_HIP(hipStreamSynchronize(st));
     ring.reset();
+    return FM_OK;
+  };
+
+  std::vector<double> scale(batch, 1.0);
+  {
+    std::vector<int> ids;
+    std::vector<const double*> a;
+    for (int i : which)
+      if (inst[i].kind == FM_FLOW_SQRT_STEADY) {
+        ids.push_back(i);
+        a.push_back(inst[i].A64);
+      }
+    FM_TRY(dots(ids, a, a, nrm));
+    FM_TRY(fetch(nrm));
+    for (int i : which)
+      scale[i] = inst[i].kind == FM_FLOW_SQRT_STEADY ? std::sqrt(hredu[i]) : std::sqrt((double)inst[i].n);
+  }
+
+  std::vector<int> active = which;
+  std::vector<int> steps(batch, 0);
+  bool first = true;
+  while (!active.empty()) {
     // residuals
     std::vector<GItem> items;
     std::vector<int> ii;
@@ -955,11 +1148,13 @@ fm_status Flow::refine(const std::vector<int>& which, std::vector<double*>& X, c
       ii.push_back(i);
     }
     FM_TRY(gemm_groups(EPI_AFFINE, items, ii, true, st));
-    for (int i : active)
-      FM_HIP(launch_dot(R[i], R[i], (int64_t)inst[i].np * inst[i].np, part, 64, part + 4096 + i, st));
-    FM_HIP(hipMemcpyAsync(hredu, part + 4096, batch * sizeof(double), hipMemcpyDeviceToHost, st));
-    FM_HIP(hipStreamSynchronize(st));
-    std::vector<int> next;
+    {
+      std::vector<const double*> a;
+      for (int i : active) a.push_back(R[i]);
+      FM_TRY(dots(active, a, a, nrm));
+      FM_TRY(fetch(nrm));
+    }
+    std::vector<int> next, next_inv, next_sqrt;
     for (int i : active) {
       const double res = std::sqrt(hredu[i]) / scale[i];
       if (stats) {
@@ -967,50 +1162,321 @@ fm_status Flow::refine(const std::vector<int>& which, std::vector<double*>& X, c
         stats[i].residual = res;
         stats[i].refine_steps = steps[i];
       }
-      if (res > prm[i].refine_tol && steps[i] < prm[i].max_refine) next.push_back(i);
+      if (res > prm[i].refine_tol && steps[i] < prm[i].max_refine) {
+        next.push_back(i);
+        (inst[i].kind == FM_FLOW_SQRT_STEADY ? next_sqrt : next_inv).push_back(i);
+      }
     }
     first = false;
     if (next.empty()) break;
-    // updates
-    std::vector<GItem> upd;
-    std::vector<int> ui;
-    for (int i : next) {
-      const Inst& in = inst[i];
-      if (in.kind == FM_FLOW_SQRT_STEADY) {
-        set_error("square-root refinement is not available in this build");
-        return FM_ERR_UNSUPPORTED;
+    // Newton-Schulz: X2 = X + X R
+    {
+      std::vector<GItem> upd;
+      std::vector<int> ui;
+      for (int i : next_inv) {
+        GItem g = blank_item(inst[i], i);
+        g.a = X[i];
+        g.b = R[i];
+        g.in0 = X[i];
+        g.out0 = X2[i];
+        g.s[0] = 1.0;
+        g.s[1] = 1.0;
+        g.flags = F_OUT0_F64 | F_E_F64;
+        upd.push_back(g);
+        ui.push_back(i);
       }
-      GItem g = blank_item(in, i);  // X2 = X + X R
-      g.a = X[i];
-      g.b = R[i];
-      g.in0 = X[i];
-      g.out0 = X2[i];
-      g.s[0] = 1.0;
-      g.s[1] = 1.0;
-      g.flags = F_OUT0_F64 | F_E_F64;
-      upd.push_back(g);
-      ui.push_back(i);
+      FM_TRY(gemm_groups(EPI_AFFINE, upd, ui, true, st));
     }
-    FM_TRY(gemm_groups(EPI_AFFINE, upd, ui, true, st));
+    // Newton for the root: CG on X H + H X = R, then X2 = X + H
+    if (!next_sqrt.empty()) {
+      std::vector<CgItem> cg;
+      for (int i : next_sqrt) cg.push_back(CgItem{H[i], r[i], p[i], R[i], (int64_t)inst[i].np * inst[i].np, i, 0});
+      void* d = nullptr;
+      FM_TRY(push(cg.data(), cg.size() * sizeof(CgItem), &d, st));
+      FM_HIP(launch_cg_init((const CgItem*)d, (int)cg.size(), st));
+      std::vector<int> cg_act = next_sqrt;
+      {
+        std::vector<const double*> a;
+        for (int i : cg_act) a.push_back(r[i]);
+        FM_TRY(dots(cg_act, a, a, rrA));
+        FM_TRY(fetch(rrA));
+      }
+      std::vector<double> rr0(batch, 0.0);
+      for (int i : cg_act) rr0[i] = hredu[i];
+      double* rr_cur = rrA;
+      double* rr_nxt = rrB;
+      const int max_cg = 600;
+      const double cg_tol = 1e-13;
+      for (int it = 0; it < max_cg && !cg_act.empty(); ++it) {
+        std::vector<GItem> g1, g2;
+        std::vector<int> i1;
+        std::vector<CgItem> ci;
+        std::vector<const double*> pa, apa, ra;
+        for (int i : cg_act) {
+          GItem a = blank_item(inst[i], i);  // T = X p
+          a.a = X[i];
+          a.b = p[i];
+          a.out0 = T[i];
+          a.s[0] = 1.0;
+          a.flags = F_OUT0_F64 | F_E_NONE;
+          g1.push_back(a);
+          GItem b = blank_item(inst[i], i);  // Ap = p X + T
+          b.a = p[i];
+          b.b = X[i];
+          b.in0 = T[i];
+          b.out0 = Ap[i];
+          b.s[0] = 1.0;
+          b.s[1] = 1.0;
+          b.flags = F_OUT0_F64 | F_E_F64;
+          g2.push_back(b);
+          i1.push_back(i);
+          ci.push_back(CgItem{H[i], r[i], p[i], Ap[i], (int64_t)inst[i].np * inst[i].np, i, 0});
+          pa.push_back(p[i]);
+          apa.push_back(Ap[i]);
+          ra.push_back(r[i]);
+        }
+        FM_TRY(gemm_groups(EPI_AFFINE, g1, i1, true, st));
+        FM_TRY(gemm_groups(EPI_AFFINE, g2, i1, true, st));
+        FM_TRY(dots(cg_act, pa, apa, pap));
+        void* dci = nullptr;
+        FM_TRY(push(ci.data(), ci.size() * sizeof(CgItem), &dci, st));
+        FM_HIP(launch_cg_step1((const CgItem*)dci, (int)ci.size(), rr_cur, pap, st));
+        FM_TRY(dots(cg_act, ra, ra, rr_nxt));
+        if (it % 8 == 7 || it == max_cg - 1) {
+          FM_TRY(fetch(rr_nxt));
+          std::vector<int> keep;
+          for (int i : cg_act)
+            if (!(std::sqrt(hredu[i]) <= cg_tol * std::sqrt(rr0[i]))) keep.push_back(i);
+          // continue with the unconverged problems only; the ring was reset
+          // by the read-back, so the list is pushed again
+          cg_act = keep;
+          ci.clear();
+          for (int i : cg_act) ci.push_back(CgItem{H[i], r[i], p[i], Ap[i], (int64_t)inst[i].np * inst[i].np, i, 0});
+          if (!ci.empty()) FM_TRY(push(ci.data(), ci.size() * sizeof(CgItem), &dci, st));
+        }
+        if (!ci.empty()) FM_HIP(launch_cg_step2((const CgItem*)dci, (int)ci.size(), rr_nxt, rr_cur, st));
+        std::swap(rr_cur, rr_nxt);
+      }
+      std::vector<CgItem> add;
+      for (int i : next_sqrt) {
+        FM_HIP(copy_f64(X2[i], X[i], (int64_t)inst[i].np * inst[i].np, st));
+        add.push_back(CgItem{X2[i], nullptr, nullptr, H[i], (int64_t)inst[i].np * inst[i].np, i, 0});
+      }
+      void* da = nullptr;
+      FM_TRY(push(add.data(), add.size() * sizeof(CgItem), &da, st));
+      FM_HIP(launch_add((const CgItem*)da, (int)add.size(), st));
+    }
     for (int i : next) {
       std::swap(X[i], X2[i]);
       steps[i]++;
     }
     active = next;
   }
-  // results that ended in the refinement scratch are copied by the caller
-  // from X[i]; keep the scratch alive until then (prop is not reused before).
+  // X[i] may now point into the refinement scratch; the caller copies it out
+  // before the scratch is reused.
   return FM_OK;
 }
 
-fm_status Flow::learned_coeffs(int, double, double, double*) const {
-  set_error("learned coarse step is not available in this build");
-  return FM_ERR_UNSUPPORTED;
+void euler_coeffs(int kind, double h, double* c) {
+  for (int q = 0; q < 8; ++q) c[q] = 0.0;
+  c[0] = kind == FM_FLOW_INV_STEADY ? 1.0 + h : 1.0;
+  c[1] = -1.0;
 }
 
-fm_status Flow::load_model(const std::string&) {
-  set_error("learned coarse model loading is not available in this build");
-  return FM_ERR_UNSUPPORTED;
+fm_status Flow::set_model(int kind, const double* theta, const double* norm) {
+  const int np = mlp_param_count();
+  model.kind = kind;
+  model.theta.assign(theta, theta + np);
+  for (int q = 0; q < 12; ++q) model.norm[q] = norm[q];
+  for (int q = 6; q < 12; ++q)
+    if (!(model.norm[q] > 0)) {
+      set_error("network input std must be positive");
+      return FM_ERR_INVALID;
+    }
+  std::vector<float> tf(theta, theta + np), nf(norm, norm + 12);
+  if (!model.d_theta) FM_HIP(hipMalloc((void**)&model.d_theta, np * sizeof(float)));
+  if (!model.d_norm) FM_HIP(hipMalloc((void**)&model.d_norm, 12 * sizeof(float)));
+  FM_HIP(hipMemcpy(model.d_theta, tf.data(), np * sizeof(float), hipMemcpyHostToDevice));
+  FM_HIP(hipMemcpy(model.d_norm, nf.data(), 12 * sizeof(float), hipMemcpyHostToDevice));
+  model.loaded = true;
+  return FM_OK;
+}
+
+// Weight file: 8-byte magic "FMMLP001", int32 kind, int32 count (9288),
+// double norm[12] (input mean[6], std[6]), double theta[count]; little endian.
+fm_status Flow::load_model(const std::string& path) {
+  FILE* f = fopen(path.c_str(), "rb");
+  if (!f) {
+    set_error("cannot open coarse model %s", path.c_str());
+    return FM_ERR_INVALID;
+  }
+  char magic[8];
+  int32_t kind = 0, count = 0;
+  double norm[12];
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "FMMLP001", 8) == 0 && fread(&kind, 4, 1, f) == 1 &&
+            fread(&count, 4, 1, f) == 1 && count == mlp_param_count() && fread(norm, 8, 12, f) == 12;
+  std::vector<double> th(count > 0 ? count : 0);
+  ok = ok && fread(th.data(), 8, count, f) == (size_t)count;
+  fclose(f);
+  if (!ok) {
+    set_error("coarse model %s is not a valid weight file", path.c_str());
+    return FM_ERR_INVALID;
+  }
+  return set_model(kind, th.data(), norm);
+}
+
+// mu_j = tr((A - I)^j) / n from M = A - I and M^2 (one FP64 product each).
+fm_status Flow::ensure_moments(hipStream_t st) {
+  for (int i = 0; i < batch; ++i) {
+    Inst& in = inst[i];
+    if (in.mu_ready) continue;
+    const size_t np2 = (size_t)in.np * in.np;
+    double *M = nullptr, *M2 = nullptr, *out = nullptr;
+    FM_HIP(hipMalloc((void**)&M, np2 * 8));
+    FM_HIP(hipMalloc((void**)&M2, np2 * 8));
+    FM_HIP(hipMalloc((void**)&out, 4 * 8));
+    fm_status s = FM_OK;
+    hipError_t e = convert_f64(M, DT_F64, in.A64, -1.0, in.n, in.np, st);
+    if (e == hipSuccess) {
+      std::vector<GItem> it(1, GItem{});
+      it[0].np = in.np;
+      it[0].n = in.n;
+      it[0].inst = i;
+      it[0].a = M;
+      it[0].b = M;
+      it[0].out0 = M2;
+      it[0].s[0] = 1.0;
+      it[0].flags = F_OUT0_F64 | F_E_NONE;
+      std::vector<int> ii(1, i);
+      s = gemm_groups(EPI_AFFINE, it, ii, true, st);
+      if (s == FM_OK) e = trace_moments(M, M2, in.n, in.np, out, st);
+      if (s == FM_OK && e == hipSuccess) e = hipMemcpyAsync(in.mu, out, 4 * 8, hipMemcpyDeviceToHost, st);
+      if (s == FM_OK && e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    (void)hipFree(M);
+    (void)hipFree(M2);
+    (void)hipFree(out);
+    if (s != FM_OK) return s;
+    if (e != hipSuccess) return hip_status(e, "trace moments");
+    in.mu_ready = true;
+  }
+  ring.reset();
+  return FM_OK;
+}
+
+fm_status Flow::learned_table(const std::vector<CoefRow>& rows, double* coef, hipStream_t st) {
+  if (!model.loaded) {
+    set_error("learned coarse step requested but no coarse model is loaded");
+    return FM_ERR_INVALID;
+  }
+  if (rows.empty()) return FM_OK;
+  FM_TRY(ensure_moments(st));
+  const int64_t S = (int64_t)rows.size();
+  std::vector<float> X(S * 6);
+  for (int64_t r = 0; r < S; ++r) {
+    const Inst& in = inst[rows[r].inst];
+    X[r * 6 + 0] = (float)rows[r].t;
+    X[r * 6 + 1] = (float)rows[r].h;
+    for (int q = 0; q < 4; ++q) X[r * 6 + 2 + q] = (float)in.mu[q];
+  }
+  float *dX = nullptr, *dY = nullptr;
+  FM_HIP(hipMalloc((void**)&dX, S * 6 * sizeof(float)));
+  hipError_t e = hipMalloc((void**)&dY, S * 8 * sizeof(float));
+  std::vector<float> Y(S * 8);
+  if (e == hipSuccess) e = hipMemcpyAsync(dX, X.data(), S * 6 * sizeof(float), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = mlp_forward(model.d_theta, model.d_norm, dX, S, dY, nullptr, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(Y.data(), dY, S * 8 * sizeof(float), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dX);
+  if (dY) (void)hipFree(dY);
+  if (e != hipSuccess) return hip_status(e, "network inference");
+  for (int64_t r = 0; r < S; ++r) {
+    euler_coeffs(inst[rows[r].inst].kind, rows[r].h, coef + r * 8);
+    for (int q = 0; q < 8; ++q) coef[r * 8 + q] += (double)Y[r * 8 + q];
+  }
+  return FM_OK;
+}
+
+// Fitting features of the learned step family for state/target pairs, one per
+// problem: K = h B X, K^2, K^3, X K, X K^2, X K^3 by FP64 products, then the
+// Gram data of the basis (see mlp.hip).
+fm_status Flow::features(double h, const double* const* X, const double* const* FX, double* G, double* bD,
+                         double* fD, double* fn, int64_t row0, hipStream_t st) {
+  for (int i = 0; i < batch; ++i)
+    if (inst[i].kind == FM_FLOW_SQRT_STEADY) {
+      set_error("learned-step features are defined for the inverse flows only");
+      return FM_ERR_UNSUPPORTED;
+    }
+  struct Buf {
+    double *B, *x, *f, *k[3], *xk[3];
+  };
+  std::vector<Buf> b(batch);
+  double* part = nullptr;
+  const int nblk = 16;
+  for (int pass = 0; pass < 2; ++pass) {
+    prop.measuring = (pass == 0);
+    prop.used = 0;
+    for (int i = 0; i < batch; ++i) {
+      const size_t np2 = (size_t)inst[i].np * inst[i].np * 8;
+      b[i].B = (double*)prop.take(np2);
+      b[i].x = (double*)prop.take(np2);
+      b[i].f = (double*)prop.take(np2);
+      for (int q = 0; q < 3; ++q) {
+        b[i].k[q] = (double*)prop.take(np2);
+        b[i].xk[q] = (double*)prop.take(np2);
+      }
+    }
+    part = (double*)prop.take((size_t)batch * nblk * 46 * 8);
+    if (pass == 0) {
+      FM_HIP(hipStreamSynchronize(st));
+      FM_TRY(prop.reserve(prop.used));
+    }
+  }
+  ring.reset();
+  std::vector<int> ii(batch);
+  for (int i = 0; i < batch; ++i) {
+    ii[i] = i;
+    FM_HIP(convert_f64(b[i].B, DT_F64, inst[i].A64, inst[i].kind == FM_FLOW_INV_HOMOTOPY ? -1.0 : 0.0, inst[i].n,
+                       inst[i].np, st));
+    FM_HIP(copy_in(b[i].x, inst[i].np, X[i], inst[i].n, st));
+    FM_HIP(copy_in(b[i].f, inst[i].np, FX[i], inst[i].n, st));
+  }
+  auto prod = [&](int which, double scale) -> fm_status {
+    std::vector<GItem> it;
+    for (int i = 0; i < batch; ++i) {
+      GItem g = blank_item(inst[i], i);
+      g.s[0] = scale;
+      g.flags = F_OUT0_F64 | F_E_NONE;
+      switch (which) {
+        case 0: g.a = b[i].B; g.b = b[i].x; g.out0 = b[i].k[0]; break;      // K = h B X
+        case 1: g.a = b[i].k[0]; g.b = b[i].k[0]; g.out0 = b[i].k[1]; break;  // K^2
+        case 2: g.a = b[i].k[1]; g.b = b[i].k[0]; g.out0 = b[i].k[2]; break;  // K^3
+        default: g.a = b[i].x; g.b = b[i].k[which - 3]; g.out0 = b[i].xk[which - 3];  // X K^j
+      }
+      it.push_back(g);
+    }
+    return gemm_groups(EPI_AFFINE, it, ii, true, st);
+  };
+  FM_TRY(prod(0, h));
+  for (int w = 1; w < 6; ++w) FM_TRY(prod(w, 1.0));
+  std::vector<FeatItem> fi(batch);
+  for (int i = 0; i < batch; ++i) {
+    FeatItem& q = fi[i];
+    q.x = b[i].x;
+    for (int j = 0; j < 3; ++j) {
+      q.xk[j] = b[i].xk[j];
+      q.k[j] = b[i].k[j];
+    }
+    q.f = b[i].f;
+    euler_coeffs(inst[i].kind, h, q.ce);
+    q.np = inst[i].np;
+    q.n = inst[i].n;
+    q.out = row0 + i;
+  }
+  void* d = nullptr;
+  FM_TRY(push(fi.data(), fi.size() * sizeof(FeatItem), &d, st));
+  FM_HIP(::fm::features((const FeatItem*)d, batch, part, nblk, G, bD, fD, fn, st));
+  return FM_OK;
 }
 
 }  // namespace fm

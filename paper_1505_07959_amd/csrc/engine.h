@@ -62,13 +62,19 @@ struct Ring {
 struct Model {
   bool loaded = false;
   int kind = 0;                 // flow kind it was trained for
-  std::vector<double> theta;    // 9288 parameters (layout of the training script)
-  double mean[6] = {0}, stdv[6] = {1, 1, 1, 1, 1, 1};
+  std::vector<double> theta;    // 9288 parameters, layer by layer (W out x in row-major, then b)
+  double norm[12] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1};  // mean[6], std[6] of the inputs
+  float* d_theta = nullptr;     // FP32 device copies used by the network kernels
+  float* d_norm = nullptr;
 };
+
+// Euler coefficients of the learned step family for `kind` and step h.
+void euler_coeffs(int kind, double h, double* c);
 
 struct Inst {
   int kind = 0;
   int n = 0, np = 0;
+  bool mu_ready = false;
   GemmCfg cfg{};     // product config in the flow dtype
   GemmCfg cfg64{};   // FP64 config (residual / refinement)
   double* A64 = nullptr;  // padded FP64 A
@@ -121,6 +127,7 @@ struct Flow {
 
   // optional HIP-event timing of the fine propagator (option timing=1)
   bool timing = false;
+  bool verbose = false;  // option verbose=1: one stderr line per parareal iteration
   std::vector<hipEvent_t> ev;      // event pool
   size_t ev_used = 0;
   std::vector<std::pair<int, double>> ev_pairs;  // (index of start event, flops) of RK4-epilogue launches
@@ -144,7 +151,16 @@ struct Flow {
 
   fm_status run_fine(const std::vector<FineSlot>& slots, int steps, hipStream_t st);
   fm_status run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipStream_t st);
-  fm_status learned_coeffs(int i, double t0, double h, double* c) const;
+  // coefficients for rows (problem, t, h): c = c_Euler(h) + net(t, h, mu)
+  struct CoefRow {
+    int inst;
+    double t, h;
+  };
+  fm_status learned_table(const std::vector<CoefRow>& rows, double* coef, hipStream_t st);
+  fm_status ensure_moments(hipStream_t st);
+  fm_status features(double h, const double* const* X, const double* const* FX, double* G, double* bD,
+                     double* fD, double* fn, int64_t row0, hipStream_t st);
+  fm_status set_model(int kind, const double* theta, const double* norm);
 
   fm_status fine_propagate(double t1, double t0, int steps, const double* const* xin, double* const* xout,
                            hipStream_t st);

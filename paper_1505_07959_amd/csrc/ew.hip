@@ -175,7 +175,103 @@ __global__ void k_axpy_dev(double* __restrict__ y, const double* __restrict__ x,
     y[e] += a * x[e];
 }
 
+// grid = (nblk, nitems)
+__global__ void k_dots_part(const DotItem* __restrict__ items, double* __restrict__ part) {
+  __shared__ double sh[EW_THREADS];
+  const DotItem it = items[blockIdx.y];
+  double s = 0.0;
+  if (it.sub) {
+    for (int64_t e = blockIdx.x * (int64_t)EW_THREADS + threadIdx.x; e < it.count; e += (int64_t)gridDim.x * EW_THREADS)
+      s += (it.a[e] - it.sub[e]) * (it.b[e] - it.sub[e]);
+  } else {
+    for (int64_t e = blockIdx.x * (int64_t)EW_THREADS + threadIdx.x; e < it.count; e += (int64_t)gridDim.x * EW_THREADS)
+      s += it.a[e] * it.b[e];
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+// grid = nitems
+__global__ void k_dots_reduce(const DotItem* __restrict__ items, const double* __restrict__ part, int nblk,
+                              double* __restrict__ out) {
+  __shared__ double sh[EW_THREADS];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += EW_THREADS) s += part[(int64_t)blockIdx.x * nblk + i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[items[blockIdx.x].slot] = s;
+}
+
+__global__ void k_cg_init(const CgItem* __restrict__ items) {
+  const CgItem it = items[blockIdx.y];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < it.count; e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = it.ap[e];
+    it.h[e] = 0.0;
+    it.r[e] = v;
+    it.p[e] = v;
+  }
+}
+
+__global__ void k_add(const CgItem* __restrict__ items) {
+  const CgItem it = items[blockIdx.y];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < it.count; e += (int64_t)gridDim.x * blockDim.x)
+    it.h[e] += it.ap[e];
+}
+
+__global__ void k_cg_step1(const CgItem* __restrict__ items, const double* __restrict__ rr,
+                           const double* __restrict__ pap) {
+  const CgItem it = items[blockIdx.y];
+  const double den = pap[it.slot];
+  const double a = den != 0.0 ? rr[it.slot] / den : 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < it.count; e += (int64_t)gridDim.x * blockDim.x) {
+    it.h[e] += a * it.p[e];
+    it.r[e] -= a * it.ap[e];
+  }
+}
+
+__global__ void k_cg_step2(const CgItem* __restrict__ items, const double* __restrict__ rr_new,
+                           const double* __restrict__ rr) {
+  const CgItem it = items[blockIdx.y];
+  const double den = rr[it.slot];
+  const double b = den != 0.0 ? rr_new[it.slot] / den : 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < it.count; e += (int64_t)gridDim.x * blockDim.x)
+    it.p[e] = it.r[e] + b * it.p[e];
+}
+
 }  // namespace
+
+hipError_t launch_dots(const DotItem* items, int nitems, double* part, int nblk, double* out, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dots_part, dim3(nblk, nitems), dim3(EW_THREADS), 0, st, items, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dots_reduce, dim3(nitems), dim3(EW_THREADS), 0, st, items, part, nblk, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_init(const CgItem* items, int nitems, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg_init, dim3(64, nitems), dim3(EW_THREADS), 0, st, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_add(const CgItem* items, int nitems, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add, dim3(64, nitems), dim3(EW_THREADS), 0, st, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_step1(const CgItem* items, int nitems, const double* rr, const double* pap, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg_step1, dim3(64, nitems), dim3(EW_THREADS), 0, st, items, rr, pap);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_step2(const CgItem* items, int nitems, const double* rr_new, const double* rr,
+                           hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg_step2, dim3(64, nitems), dim3(EW_THREADS), 0, st, items, rr_new, rr);
+  return hipGetLastError();
+}
 
 hipError_t stage_pad_f64(double* dst, int np, const double* src, int64_t n, int64_t ld, hipStream_t st) {
   hipLaunchKernelGGL(k_stage_pad, dim3(ew_grid((int64_t)np * np)), dim3(EW_THREADS), 0, st, dst, np, src, n, ld);

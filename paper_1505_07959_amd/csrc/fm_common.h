@@ -125,4 +125,36 @@ hipError_t launch_dot(const double* a, const double* b, int64_t count, double* p
 hipError_t launch_axpy_dev(double* y, const double* x, const double* alpha_d, double sign,
                            int64_t count, hipStream_t st);
 
+// Batched FP64 dot products: out[item.slot] = <a, b> for every item
+// (two-level, fixed order).  part needs nitems * nblk doubles.
+struct DotItem {
+  const double* a;
+  const double* b;
+  int64_t count;
+  int slot;
+  int pad_;
+  const double* sub;  // when non-null: <a - sub, b - sub>
+};
+hipError_t launch_dots(const DotItem* items, int nitems, double* part, int nblk, double* out, hipStream_t st);
+
+// Conjugate-gradient vector updates for a batch of problems (slot = problem):
+//   step1: alpha = rr[slot] / pap[slot]; h += alpha p; r -= alpha ap
+//   step2: beta = rr_new[slot] / rr[slot]; p = r + beta p
+struct CgItem {
+  double* h;
+  double* r;
+  double* p;
+  const double* ap;
+  int64_t count;
+  int slot;
+  int pad_;
+};
+// CG start: h = 0, r = src (passed in ap), p = src
+hipError_t launch_cg_init(const CgItem* items, int nitems, hipStream_t st);
+// y += x for every item (h = y, ap = x)
+hipError_t launch_add(const CgItem* items, int nitems, hipStream_t st);
+hipError_t launch_cg_step1(const CgItem* items, int nitems, const double* rr, const double* pap, hipStream_t st);
+hipError_t launch_cg_step2(const CgItem* items, int nitems, const double* rr_new, const double* rr,
+                           hipStream_t st);
+
 }  // namespace fm

@@ -80,6 +80,18 @@ def _load():
     lib.fm_last_error.restype = ctypes.c_char_p
     for f in ("fm_flow_create", "fm_parareal_solve", "fm_fine_propagate", "fm_coarse_propagate"):
         getattr(lib, f).restype = ctypes.c_int32
+    I64, F32, F64, I32 = ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.c_int32
+    lib.fm_mlp_param_count.restype = I32
+    lib.fm_mlp_forward.argtypes = [P, P, P, I64, P, P, P]
+    lib.fm_mlp_loss.argtypes = [P, P, P, P, P, P, F32, I64, P, P, P, P]
+    lib.fm_mlp_backward.argtypes = [P, P, P, P, P, I64, P, P, P]
+    lib.fm_mlp_adam.argtypes = [P, P, P, P, I64, I32, F32, P]
+    lib.fm_learned_features.argtypes = [P, F64, PP, PP, P, P, P, P, I64, P]
+    lib.fm_trace_moments.argtypes = [P, ctypes.POINTER(F64), P]
+    lib.fm_flow_set_coarse_model.argtypes = [P, I32, ctypes.POINTER(F64), ctypes.POINTER(F64)]
+    for f in ("fm_mlp_forward", "fm_mlp_loss", "fm_mlp_backward", "fm_mlp_adam", "fm_learned_features",
+              "fm_trace_moments", "fm_flow_set_coarse_model"):
+        getattr(lib, f).restype = I32
     return lib
 
 
@@ -156,3 +168,48 @@ def fm_coarse_propagate(flow, t_next, t_cur, steps, coarse, X_in, X_out, stream=
 def fm_destroy(flow):
     if flow is not None and flow.value:
         lib.fm_destroy(flow)
+
+
+# ---------------------------------------------------------------- training
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def fm_mlp_param_count():
+    return int(lib.fm_mlp_param_count())
+
+
+def fm_mlp_forward(theta, norm, X, Y, acts=None, stream=None):
+    return _check(lib.fm_mlp_forward(_p(theta), _p(norm), _p(X), int(X.shape[0]), _p(Y), _p(acts), _stream(stream)))
+
+
+def fm_mlp_loss(Y, cbase, G, bD, fD, fn, rho, dY, Ls, Lsum=None, stream=None):
+    return _check(lib.fm_mlp_loss(_p(Y), _p(cbase), _p(G), _p(bD), _p(fD), _p(fn), float(rho), int(Y.shape[0]),
+                                  _p(dY), _p(Ls), _p(Lsum), _stream(stream)))
+
+
+def fm_mlp_backward(theta, norm, X, acts, dY, deltas, grad, stream=None):
+    return _check(lib.fm_mlp_backward(_p(theta), _p(norm), _p(X), _p(acts), _p(dY), int(X.shape[0]), _p(deltas),
+                                      _p(grad), _stream(stream)))
+
+
+def fm_mlp_adam(theta, grad, m, v, t, lr, stream=None):
+    return _check(lib.fm_mlp_adam(_p(theta), _p(grad), _p(m), _p(v), int(theta.numel()), int(t), float(lr),
+                                  _stream(stream)))
+
+
+def fm_learned_features(flow, h, X, FX, G, bD, fD, fn, row0=0, stream=None):
+    return _check(lib.fm_learned_features(flow, float(h), _ptrs(X), _ptrs(FX), _p(G), _p(bD), _p(fD), _p(fn),
+                                          int(row0), _stream(stream)))
+
+
+def fm_trace_moments(flow, batch, stream=None):
+    out = (ctypes.c_double * (4 * batch))()
+    _check(lib.fm_trace_moments(flow, out, _stream(stream)))
+    return [list(out[4 * i:4 * i + 4]) for i in range(batch)]
+
+
+def fm_flow_set_coarse_model(flow, kind, theta, norm):
+    th = (ctypes.c_double * len(theta))(*[float(x) for x in theta])
+    nm = (ctypes.c_double * 12)(*[float(x) for x in norm])
+    return _check(lib.fm_flow_set_coarse_model(flow, int(kind), th, nm))

@@ -17,7 +17,9 @@ Workloads (sizes as in the benchmark configurations):
              {32, 64, ..., 512} (drawn first), lam ~ loguniform[1e-2, 10];
              even i inverse homotopy (T = 1), odd i square-root flow (T = 20)
 * learned:   training matrices n = 256, lam ~ loguniform[1e-2, 10], seeds
-             40000 + j; evaluation n = 2048, same law, seed 4
+             40000 + j; evaluation n = 2048, same law, seed 4; for the
+             steady inverse flow lam ~ loguniform[1e-3, 1] scaled to max 1,
+             seeds 50000 + j
 * steady:    n = 8192, lam ~ loguniform[1e-3, 1], seed 5, scaled by 1 / max lam
              so that ||A||_2 <= 1
 """
@@ -88,6 +90,11 @@ def learned_eval_problem(n=2048):
 
 def learned_train_problem(j, n=256):
     return spd(n, "loguniform", 1e-2, 10.0, 40000 + j)
+
+
+def steady_train_problem(j, n=256):
+    """Training matrices for the learned step of dX/dt = X - X A X."""
+    return spd(n, "loguniform", 1e-3, 1.0, 50000 + j, scale_to_unit=True)
 
 
 BATCHED_SIZES = tuple(range(32, 513, 32))

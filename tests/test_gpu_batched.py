@@ -1,0 +1,83 @@
+"""Batched uneven problems in one flow: inverse homotopy (T = 1) and the
+square-root flow dX/dt = A - X^2 (T = 20) mixed, n in {32, ..., 512},
+lam ~ loguniform[1e-2, 10], BF16 products with FP32 accumulation, FP64
+correction, then FP64 refinement (Newton-Schulz / Newton with a CG Sylvester
+solve).  Reference: the spectral FP64 oracle of the same discrete method
+(exact for symmetric A with X0 = I) and the exact f(A)."""
+
+import numpy as np
+import pytest
+
+from oracle import SpectralAlgebra, HOMOTOPY, SQRT, integrators, parareal
+from paper_1505_07959_amd import inputs
+from tests.gpu_util import dev, host, empty, rel, say
+
+pytestmark = pytest.mark.gpu
+
+N_SLICES, FINE, TOL = 64, 8, 1e-3
+COARSE = {HOMOTOPY: 1, SQRT: 2}
+
+
+def _params(kind, T, refine):
+    return {"T": T, "N": N_SLICES, "fine_steps": FINE, "coarse_steps": COARSE[kind], "max_iter": 12, "tol": TOL,
+            "max_refine": 6 if refine else 0, "refine_tol": 1e-13}
+
+
+def _oracle(kind, T, Q, lam, iters):
+    alg = SpectralAlgebra(Q, lam)
+    t = [i * T / N_SLICES for i in range(N_SLICES + 1)]
+    F = lambda i, x: integrators.fine(alg, kind, lam, x, t[i + 1], t[i], FINE)
+    G = lambda i, x: integrators.coarse(alg, kind, lam, x, t[i + 1], t[i], COARSE[kind])
+    return parareal.parareal(F, G, alg.eye(), N_SLICES, iters, 0.0, alg.fro)
+
+
+def _exact(kind, Q, lam):
+    f = 1.0 / lam if kind == HOMOTOPY else np.sqrt(lam)
+    return (Q * f) @ Q.T
+
+
+def _run(cases, dtype, refine):
+    from paper_1505_07959_amd import fm
+    h = fm.fm_flow_create([(k, dev(A)) for k, T, A, Q, lam in cases], dtype)
+    try:
+        outs = [empty(A.shape[0]) for _, _, A, _, _ in cases]
+        st, stats = fm.fm_parareal_solve(h, None, outs, [_params(k, T, refine) for k, T, *_ in cases])
+        return st, stats, [host(o) for o in outs]
+    finally:
+        fm.fm_destroy(h)
+
+
+def test_batched_bf16_before_and_after_refinement():
+    cases = [inputs.batched_instance(i, max_n=256) for i in range(12)]
+    say("sizes %s" % [c[2].shape[0] for c in cases])
+    st0, stats0, X0 = _run(cases, "bf16", refine=False)
+    st1, stats1, X1 = _run(cases, "bf16", refine=True)
+    worst_pre = {HOMOTOPY: 0.0, SQRT: 0.0}
+    for (kind, T, A, Q, lam), s0, x0, s1, x1 in zip(cases, stats0, X0, stats1, X1):
+        ref = _oracle(kind, T, Q, lam, s0["iters"])
+        salg = SpectralAlgebra(Q, lam)
+        e_pre = rel(x0, salg.to_matrix(ref["U"][-1]))
+        e_post = rel(x1, _exact(kind, Q, lam))
+        worst_pre[kind] = max(worst_pre[kind], e_pre)
+        say("  kind %d n %3d iters %2d pre %.2e post %.2e (residual %.1e -> %.1e in %d steps)" %
+            (kind, A.shape[0], s0["iters"], e_pre, e_post, s1["residual_before"], s1["residual"],
+             s1["refine_steps"]))
+        assert s1["iters"] == s0["iters"]
+        assert e_post <= 1e-10
+    say("worst pre-refinement error: inverse %.2e, square root %.2e" % (worst_pre[HOMOTOPY], worst_pre[SQRT]))
+    assert worst_pre[SQRT] <= 1e-2
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batched_matches_oracle_iterates(dtype):
+    """Same batch in FP64/FP32: the GPU iterate after the reported number of
+    iterations equals the oracle's to the dtype bar."""
+    cases = [inputs.batched_instance(i, max_n=192) for i in range(6)]
+    st, stats, X = _run(cases, dtype, refine=False)
+    bar = 1e-10 if dtype == "f64" else 1e-5
+    for (kind, T, A, Q, lam), s, x in zip(cases, stats, X):
+        ref = _oracle(kind, T, Q, lam, s["iters"])
+        e = rel(x, SpectralAlgebra(Q, lam).to_matrix(ref["U"][-1]))
+        say("  %s kind %d n %3d iters %d err %.2e" % (dtype, kind, A.shape[0], s["iters"], e))
+        assert s["iters"] == ref["iters"]
+        assert e <= bar

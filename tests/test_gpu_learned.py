@@ -1,0 +1,176 @@
+"""GPU kernels of the learned coarse step against the FP64 oracle: network
+forward/loss/backward/Adam, fitting features, trace moments, and learned
+parareal (with a network whose output is exact in FP32) end to end."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import MatrixAlgebra, SpectralAlgebra, HOMOTOPY, STEADY_INV
+from oracle import mlp, learned, integrators, parareal
+from paper_1505_07959_amd import inputs
+from tests.gpu_util import dev, host, empty, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _f32(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def _net_case(S=300, seed=0):
+    rng = np.random.default_rng(seed)
+    theta = inputs.mlp_init(seed + 1) + 0.05 * rng.standard_normal(9288)
+    theta = theta.astype(np.float32).astype(np.float64)   # exactly representable on both sides
+    Xin = np.column_stack([rng.uniform(0, 1, S), rng.uniform(0.004, 0.04, S), rng.normal(size=(S, 4))])
+    Xin = Xin.astype(np.float32).astype(np.float64)
+    norm = np.concatenate([Xin.mean(0), Xin.std(0)]).astype(np.float32).astype(np.float64)
+    return theta, Xin, norm
+
+
+def test_forward_matches_oracle():
+    from paper_1505_07959_amd import fm
+    theta, Xin, norm = _net_case()
+    Y = torch.empty((Xin.shape[0], 8), dtype=torch.float32, device="cuda")
+    fm.fm_mlp_forward(_f32(theta), _f32(norm), _f32(Xin), Y)
+    Z = (Xin - norm[:6]) / norm[6:]
+    ref, _ = mlp.forward(theta, Z)
+    e = rel(host(Y).astype(np.float64), ref)
+    say("forward rel err %.2e" % e)
+    assert e <= 1e-5
+
+
+def test_loss_and_backward_match_oracle():
+    from paper_1505_07959_amd import fm
+    theta, Xin, norm = _net_case(S=257, seed=3)
+    S = Xin.shape[0]
+    rng = np.random.default_rng(5)
+    Bm = rng.standard_normal((S, 8, 8))
+    G = np.einsum("sab,scb->sac", Bm, Bm) + 0.1 * np.eye(8)
+    b = rng.standard_normal((S, 8))
+    f = rng.uniform(1.0, 2.0, S)
+    cbase = np.tile(np.array([1.0, -1.0, 0, 0, 0.25, 0, 0, 0]), (S, 1))
+    rho = 0.01
+    # defect data relative to cbase, as the feature kernel writes it
+    bD = b - np.einsum("sab,sb->sa", G, cbase)
+    fD = f - 2 * np.einsum("sa,sa->s", b, cbase) + np.einsum("sa,sab,sb->s", cbase, G, cbase)
+    Y = torch.empty((S, 8), dtype=torch.float32, device="cuda")
+    acts = torch.empty((S, 192), dtype=torch.float32, device="cuda")
+    dY = torch.empty((S, 8), dtype=torch.float32, device="cuda")
+    Ls = torch.empty((S,), dtype=torch.float64, device="cuda")
+    Lsum = torch.empty((1,), dtype=torch.float64, device="cuda")
+    deltas = torch.empty((S, 192), dtype=torch.float32, device="cuda")
+    grad = torch.empty((9288,), dtype=torch.float32, device="cuda")
+    th, nm, xx = _f32(theta), _f32(norm), _f32(Xin)
+    fm.fm_mlp_forward(th, nm, xx, Y, acts)
+    fm.fm_mlp_loss(Y, _f32(cbase), dev(G.reshape(S, 64)), dev(bD), dev(fD), dev(f), rho, dY, Ls, Lsum)
+    fm.fm_mlp_backward(th, nm, xx, acts, dY, deltas, grad)
+    Z = (Xin - norm[:6]) / norm[6:]
+    L_ref, g_ref = mlp.loss_grad(theta, Z, cbase, G, b, f, rho=rho)
+    L_gpu = float(host(Lsum)[0]) / S
+    say("loss %.6e vs %.6e ; grad rel err %.2e" % (L_gpu, L_ref, rel(host(grad).astype(np.float64), g_ref)))
+    assert abs(L_gpu - L_ref) <= 1e-5 * abs(L_ref)
+    assert rel(host(grad).astype(np.float64), g_ref) <= 1e-4
+
+
+def test_adam_matches_oracle():
+    from paper_1505_07959_amd import fm
+    rng = np.random.default_rng(9)
+    th = rng.standard_normal(9288).astype(np.float32).astype(np.float64)
+    g = rng.standard_normal(9288).astype(np.float32).astype(np.float64)
+    m = np.zeros(9288)
+    v = np.zeros(9288)
+    tt, mm, vv = _f32(th), _f32(m), _f32(v)
+    for t in (1, 2, 3):
+        fm.fm_mlp_adam(tt, _f32(g), mm, vv, t, 1e-3)
+        th, m, v = mlp.adam_step(th, g, m, v, t, 1e-3)
+    assert rel(host(tt).astype(np.float64), th) <= 1e-6
+
+
+@pytest.mark.parametrize("kind", [HOMOTOPY, STEADY_INV])
+def test_features_match_oracle(kind):
+    from paper_1505_07959_amd import fm
+    n, h = 72, 1.0 / 16
+    A, Q, lam = inputs.spd(n, "loguniform", 1e-2, 10.0, 41)
+    X = inputs.perturbed_identity(n, 42, 0.05)
+    FX = integrators.fine(MatrixAlgebra(n), kind, A, X, h, 0.0, 4)
+    G0, b0, f0 = learned.features(MatrixAlgebra(n), kind, A, X, FX, h)
+    ce = learned.euler_coeffs(kind, h)
+    flow = fm.fm_flow_create([(kind, dev(A))], "f64")
+    try:
+        G = torch.empty((3, 64), dtype=torch.float64, device="cuda")
+        bD = torch.empty((3, 8), dtype=torch.float64, device="cuda")
+        fD = torch.empty((3,), dtype=torch.float64, device="cuda")
+        fn = torch.empty((3,), dtype=torch.float64, device="cuda")
+        fm.fm_learned_features(flow, h, [dev(X)], [dev(FX)], G, bD, fD, fn, row0=1)
+        mu = fm.fm_trace_moments(flow, 1)[0]
+    finally:
+        fm.fm_destroy(flow)
+    Gg = host(G)[1].reshape(8, 8)
+    assert rel(Gg, G0) <= 1e-12
+    assert rel(host(bD)[1], b0 - G0 @ ce) <= 1e-9
+    fD_ref = f0 - 2 * b0 @ ce + ce @ G0 @ ce
+    D = FX - learned.poly_step(MatrixAlgebra(n), kind, A, X, h, ce)
+    assert abs(fD_ref - np.sum(D * D)) <= 1e-6 * fD_ref     # the oracle's two routes agree
+    assert abs(host(fD)[1] - np.sum(D * D)) <= 1e-9 * np.sum(D * D)
+    assert abs(host(fn)[1] - f0) <= 1e-13 * f0
+    assert np.allclose(mu, [np.mean((lam - 1) ** j) for j in (1, 2, 3, 4)], rtol=1e-10)
+
+
+@pytest.mark.parametrize("kind,T,N,S,dtype,bar", [(HOMOTOPY, 1.0, 16, 8, "f64", 1e-10),
+                                                   (STEADY_INV, 24.0, 16, 8, "f64", 1e-10),
+                                                   (HOMOTOPY, 1.0, 16, 8, "f32", 1e-5)])
+def test_learned_parareal_matches_oracle(kind, T, N, S, dtype, bar):
+    """A network whose output is its last bias (exact in FP32): both sides use
+    the same coefficients c = c_Euler(h) + b4, including the fallback choice."""
+    from paper_1505_07959_amd import fm
+    n = 128
+    A, Q, lam = inputs.spd(n, "loguniform", 1e-2, 10.0, 51) if kind == HOMOTOPY else \
+        inputs.spd(n, "loguniform", 1e-3, 1.0, 52, scale_to_unit=True)
+    theta = np.zeros(9288)
+    b4 = np.array([0.0, 0.0, 0.5, -0.5, 0.0, 0.0, 0.0, 0.0])   # towards the Taylor member
+    theta[-8:] = b4
+    norm = np.concatenate([np.zeros(6), np.ones(6)])
+    salg = SpectralAlgebra(Q, lam)
+    ref = learned.parareal_learned(salg, kind, lam, salg.eye(), T, N, 1, S, 6, 0.0,
+                                   lambda t, h: learned.euler_coeffs(kind, h) + b4)
+    flow = fm.fm_flow_create([(kind, dev(A))], dtype)
+    try:
+        fm.fm_flow_set_coarse_model(flow, kind, theta, norm)
+        out = empty(n)
+        st, stats = fm.fm_parareal_solve(flow, None, [out], [{"T": T, "N": N, "fine_steps": S, "max_iter": 6,
+                                                              "tol": 0.0, "coarse": fm.FM_COARSE_LEARNED}])
+    finally:
+        fm.fm_destroy(flow)
+    e = rel(host(out), salg.to_matrix(ref["U"][-1]))
+    say("learned parareal kind %d %s: iters %d, learned slices %d (oracle %d), rel err %.2e" %
+        (kind, dtype, stats[0]["iters"], stats[0]["learned_slices"], sum(ref["choices"][-1]), e))
+    np.testing.assert_allclose(stats[0]["hist"], ref["increments"], rtol=1e-3 if dtype == "f32" else 1e-6)
+    assert e <= bar
+
+
+def test_training_pipeline_small(tmp_path):
+    """Tiny end-to-end run of the training driver: samples from GPU
+    trajectories, loss decreases below the Euler loss, model file round-trips
+    and drives a learned parareal solve."""
+    from paper_1505_07959_amd import fm, train_coarse
+    data = train_coarse.generate(HOMOTOPY, 12, 64, 1.0, [8, 16, 32], 4, 6, "f32")
+    e_loss = train_coarse.euler_loss(*data[1:])
+    theta, norm, hist = train_coarse.train(*data, epochs=30, minibatch=64, lr=3e-3, seed=1)
+    say("euler loss %.3e, trained %.3e -> %.3e" % (e_loss, hist[0], hist[-1]))
+    assert hist[-1] < 0.5 * e_loss
+    path = str(tmp_path / "m.fmw")
+    train_coarse.write_model(path, HOMOTOPY, theta, norm)
+    k2, th2, nm2 = train_coarse.read_model(path)
+    assert k2 == HOMOTOPY and np.array_equal(th2, theta) and np.array_equal(nm2, norm)
+    A, Q, lam = inputs.learned_train_problem(999, 64)
+    flow = fm.fm_flow_create([(HOMOTOPY, dev(A))], "f32", "coarse_model=" + path)
+    try:
+        out = empty(64)
+        st, stats = fm.fm_parareal_solve(flow, None, [out], [{"T": 1.0, "N": 16, "fine_steps": 8, "max_iter": 16,
+                                                              "tol": 1e-8, "coarse": fm.FM_COARSE_LEARNED}])
+        assert st == fm.FM_OK and stats[0]["iters"] < 16
+    finally:
+        fm.fm_destroy(flow)
