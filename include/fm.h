@@ -116,7 +116,8 @@ typedef struct {
    * event timing, on the solve's stream, of every launch of the fine
    * propagator's second product of an RK4 stage (the RK4-epilogue GEMM).   */
   int32_t fine_launches;   /* number of such launches */
-  int32_t reserved_;
+  int32_t learned_restarts; /* times a learned-coarse problem restarted from
+                               Step 0 with Euler after a non-finite iterate */
   double fine_ms;          /* their summed duration, milliseconds */
   double fine_flops;       /* their algorithmic flops: 2 n^3 per problem-slice */
   double fine_phase_ms;    /* duration of the whole batched fine phases */
@@ -129,7 +130,10 @@ typedef struct {
  * options: NULL or "key=value;key=value": coarse_model=<path> loads learned
  * coarse weights (file written by the training script), autotune=0|1 (default
  * 1: time candidate tile shapes on first use), autotune_cache=<path>,
- * timing=0|1 (default 0: fill the timing fields of fm_stats).
+ * timing=0|1 (default 0: fill the timing fields of fm_stats), verbose=0|1
+ * (one stderr line per parareal iteration), tile=<bm>x<bk> (fixed product
+ * tile instead of the autotuned one; ignored where it does not divide the
+ * padded order).  Tile shapes never change results, only speed.
  * out: host; receives the handle.  Returns FM_ERR_INVALID for batch < 1,
  * n out of range, lda < n, an unknown kind/dtype or a NULL A.
  */

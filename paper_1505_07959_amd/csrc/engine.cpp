@@ -12,6 +12,8 @@
 #include <cstring>
 #include <chrono>
 #include <map>
+#include <mutex>
+#include <tuple>
 
 namespace fm {
 
@@ -170,13 +172,139 @@ static int pad_order(int n) { return (n + 63) / 64 * 64; }
 
 static int default_bk(int dt) { return dt == DT_F64 ? 16 : (dt == DT_F32 ? 32 : 64); }
 
-GemmCfg Flow::pick_cfg(int d, int np) {
+static GemmCfg default_cfg(int d, int np) {
   GemmCfg c;
   c.dt = d;
   c.bk = default_bk(d);
   // 128-wide tiles once a product has enough of them to fill the GPU
   c.bm = (np % 128 == 0 && np >= 512) ? 128 : 64;
   return c;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Tile shape per (device, dtype, padded order), chosen by timing every compiled
+// configuration on a batch of products of that order (AFFINE epilogue, the
+// shape of the propagators' first product).  All configurations sum over k in
+// the same order, so the choice changes speed only, never results.  Choices are
+// kept for the process and, with autotune_cache=<file>, across processes
+// (lines "device dtype np bm bk").
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, GemmCfg> g_tune;
+static std::map<std::string, bool> g_tune_loaded;
+
+static void tune_load(const std::string& path) {
+  if (path.empty() || g_tune_loaded.count(path)) return;
+  g_tune_loaded[path] = true;
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return;
+  int dev, d, np, bm, bk;
+  while (fscanf(f, "%d %d %d %d %d", &dev, &d, &np, &bm, &bk) == 5)
+    for (const GemmCfg& c : gemm_configs(d))
+      if (c.bm == bm && c.bk == bk && np % bm == 0 && np % bk == 0) g_tune[{dev, d, np}] = c;
+  fclose(f);
+}
+
+static void tune_store(const std::string& path, int dev, int d, int np, const GemmCfg& c) {
+  if (path.empty()) return;
+  FILE* f = fopen(path.c_str(), "a");
+  if (!f) return;
+  fprintf(f, "%d %d %d %d %d\n", dev, d, np, c.bm, c.bk);
+  fclose(f);
+}
+
+static double time_cfg(const GemmCfg& c, int np, int nb, void* A, void* B, void* C, GItem* d_items, int* d_ts,
+                       hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  std::vector<GItem> items(nb);
+  std::vector<int> ts(nb + 1, 0);
+  const size_t esz = dt_size(c.dt);
+  for (int j = 0; j < nb; ++j) {
+    GItem& g = items[j];
+    memset(&g, 0, sizeof g);
+    g.a = A;
+    g.b = B;
+    g.out0 = (char*)C + (size_t)j * np * np * esz;
+    g.s[0] = 1.0;
+    g.flags = F_E_NONE;
+    g.np = np;
+    g.n = np;
+    ts[j + 1] = ts[j] + (np / c.bm) * (np / c.bm);
+  }
+  if (hipMemcpyAsync(d_items, items.data(), nb * sizeof(GItem), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(d_ts, ts.data(), (nb + 1) * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
+    return 1e30;
+  const int total = ts[nb];
+  const int grid = std::min(total, gemm_max_grid(c));
+  double best = 1e30;
+  for (int rep = 0; rep < 3; ++rep) {
+    if (hipEventRecord(e0, st) != hipSuccess) return 1e30;
+    if (launch_gemm(c, EPI_AFFINE, d_items, d_ts, nb, total, grid, nullptr, st) != hipSuccess) return 1e30;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 1e30;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 1e30;
+    if (rep > 0) best = std::min(best, (double)ms);  // first launch warms up
+  }
+  return best;
+}
+
+GemmCfg Flow::pick_cfg(int d, int np) {
+  const GemmCfg def = default_cfg(d, np);
+  if (force_bm && d == dt) {
+    for (const GemmCfg& c : gemm_configs(d))
+      if (c.bm == force_bm && c.bk == force_bk && np % c.bm == 0 && np % c.bk == 0) return c;
+    return def;
+  }
+  if (!autotune) return def;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_load(autotune_cache);
+  auto key = std::make_tuple(device, d, np);
+  auto it = g_tune.find(key);
+  if (it != g_tune.end()) return it->second;
+  std::vector<GemmCfg> cand;
+  for (const GemmCfg& c : gemm_configs(d))
+    if (np % c.bm == 0 && np % c.bk == 0) cand.push_back(c);
+  if (cand.size() <= 1) return def;
+  // a batch of products of this order large enough to fill the GPU
+  const size_t np2 = (size_t)np * np;
+  int nb = (int)std::max<size_t>(1, std::min<size_t>(16, ((size_t)1 << 27) / (np2 * 2)));
+  const size_t esz = dt_size(d);
+  void *A = nullptr, *B = nullptr, *C = nullptr;
+  GItem* di = nullptr;
+  int* dts = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  GemmCfg best_c = def;
+  bool ok = hipMalloc(&A, np2 * esz) == hipSuccess && hipMalloc(&B, np2 * esz) == hipSuccess &&
+            hipMalloc(&C, np2 * esz * nb) == hipSuccess && hipMalloc((void**)&di, nb * sizeof(GItem)) == hipSuccess &&
+            hipMalloc((void**)&dts, (nb + 1) * sizeof(int)) == hipSuccess &&
+            hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+            hipEventCreate(&e1) == hipSuccess && fill_pattern(A, d, (int64_t)np2, st) == hipSuccess &&
+            fill_pattern(B, d, (int64_t)np2, st) == hipSuccess;
+  if (ok) {
+    double best = 1e30;
+    for (const GemmCfg& c : cand) {
+      const double ms = time_cfg(c, np, nb, A, B, C, di, dts, st, e0, e1);
+      if (verbose) fprintf(stderr, "[fm] autotune dt=%d np=%d bm=%d bk=%d: %.3f ms\n", d, np, c.bm, c.bk, ms);
+      if (ms < best) {
+        best = ms;
+        best_c = c;
+      }
+    }
+    if (best >= 1e29) best_c = def;
+  }
+  if (st) (void)hipStreamSynchronize(st);
+  if (A) (void)hipFree(A);
+  if (B) (void)hipFree(B);
+  if (C) (void)hipFree(C);
+  if (di) (void)hipFree(di);
+  if (dts) (void)hipFree(dts);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) (void)hipStreamDestroy(st);
+  (void)hipGetLastError();
+  g_tune[key] = best_c;
+  tune_store(autotune_cache, device, d, np, best_c);
+  if (verbose) fprintf(stderr, "[fm] autotune dt=%d np=%d -> bm=%d bk=%d\n", d, np, best_c.bm, best_c.bk);
+  return best_c;
 }
 
 // ---------------------------------------------------------------- create
@@ -204,6 +332,10 @@ fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char*
   if (kv.count("autotune_cache")) autotune_cache = kv["autotune_cache"];
   if (kv.count("timing")) timing = kv["timing"] != "0";
   if (kv.count("verbose")) verbose = kv["verbose"] != "0";
+  if (kv.count("tile") && sscanf(kv["tile"].c_str(), "%dx%d", &force_bm, &force_bk) != 2) {
+    set_error("option tile must read <bm>x<bk>");
+    return FM_ERR_INVALID;
+  }
   FM_TRY(ring.init(size_t(256) << 20));
   inst.resize(nb);
   for (int i = 0; i < nb; ++i) {
@@ -742,6 +874,10 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
     if (X0 && X0[i]) FM_HIP(copy_in(w[i].U[0], inst[i].np, X0[i], inst[i].n, st));
     else FM_HIP(set_identity(w[i].U[0], inst[i].n, inst[i].np, st));
   }
+  // coarse propagator in use per problem: learned problems fall back to Euler
+  // for good when an iteration produced a non-finite iterate
+  std::vector<int> cmode(batch);
+  for (int i = 0; i < batch; ++i) cmode[i] = prm[i].coarse;
   auto coarse_slot = [&](int i, int s, const double* xin, double* xout, bool learned) {
     CoarseSlot c;
     const int N = prm[i].N, C = prm[i].coarse_steps;
@@ -768,74 +904,84 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
     for (auto& g : by) FM_TRY(run_coarse(g.second, g.first.second, st));
     return FM_OK;
   };
-  for (int s = 0; s < Nmax; ++s) {
-    std::vector<CoarseSlot> cs;
-    for (int i = 0; i < batch; ++i)
-      if (s < prm[i].N) cs.push_back(coarse_slot(i, s, w[i].U[s], w[i].Go[s], prm[i].coarse == FM_COARSE_LEARNED));
-    FM_TRY(run_coarse_mixed(cs));
-    for (int i = 0; i < batch; ++i)
-      if (s < prm[i].N) FM_HIP(copy_f64(w[i].U[s + 1], w[i].Go[s], (int64_t)inst[i].np * inst[i].np, st));
-  }
   const size_t npairs = (size_t)Nmax * batch;
+  FM_TRY(ensure_hredu(npairs * 3));
+  double* s0sums = nullptr;
+  double* s0part = nullptr;
   if (any_learned) {
-    // Step 0 keeps the learned value unless it is not finite: find the first
-    // non-finite slice of each learned problem and redo the sweep from there
-    // with Euler on that slice (rare path, one check per redone slice).
-    FM_TRY(ensure_hredu(npairs * 3));
-    double* sums = nullptr;
-    double* dpart = nullptr;
     for (int pass = 0; pass < 2; ++pass) {
       prop.measuring = (pass == 0);
       prop.used = 0;
-      sums = (double*)prop.take(npairs * 8);
-      dpart = (double*)prop.take(npairs * 16 * 8);
+      s0sums = (double*)prop.take(npairs * 8);
+      s0part = (double*)prop.take(npairs * 16 * 8);
       if (pass == 0) {
         FM_HIP(hipStreamSynchronize(st));
         FM_TRY(prop.reserve(prop.used));
       }
     }
-    auto norms = [&](const std::vector<std::pair<int, int>>& is) -> fm_status {
-      std::vector<DotItem> it;
-      for (auto& q : is) {
-        const int i = q.first, t = q.second;
-        it.push_back(DotItem{w[i].Go[t], w[i].Go[t], (int64_t)inst[i].np * inst[i].np, t * batch + i, 0, nullptr});
-      }
-      if (it.empty()) return FM_OK;
-      void* d = nullptr;
-      FM_TRY(push(it.data(), it.size() * sizeof(DotItem), &d, st));
-      FM_HIP(launch_dots((const DotItem*)d, (int)it.size(), dpart, 16, sums, st));
-      FM_HIP(hipMemcpyAsync(hredu, sums, npairs * sizeof(double), hipMemcpyDeviceToHost, st));
-      FM_HIP(hipStreamSynchronize(st));
-      ring.reset();
-      return FM_OK;
-    };
+  }
+  // number of non-finite entries of G_old of the listed (problem, slice) pairs
+  auto nonfinite = [&](const std::vector<std::pair<int, int>>& is) -> fm_status {
+    std::vector<DotItem> it;
+    for (auto& q : is) {
+      const int i = q.first, t = q.second;
+      it.push_back(DotItem{w[i].Go[t], w[i].Go[t], (int64_t)inst[i].np * inst[i].np, t * batch + i, 1, nullptr});
+    }
+    if (it.empty()) return FM_OK;
+    void* d = nullptr;
+    FM_TRY(push(it.data(), it.size() * sizeof(DotItem), &d, st));
+    FM_HIP(launch_dots((const DotItem*)d, (int)it.size(), s0part, 16, s0sums, st));
+    FM_HIP(hipMemcpyAsync(hredu, s0sums, npairs * sizeof(double), hipMemcpyDeviceToHost, st));
+    FM_HIP(hipStreamSynchronize(st));
+    ring.reset();
+    return FM_OK;
+  };
+  // Step 0 for the listed problems.  The learned step is kept unless it is not
+  // finite: the first non-finite slice of a learned problem is redone with
+  // Euler and the sweep continues from there (rare path, one check per slice).
+  auto step0 = [&](const std::vector<int>& ids) -> fm_status {
+    for (int s = 0; s < Nmax; ++s) {
+      std::vector<CoarseSlot> cs;
+      for (int i : ids)
+        if (s < prm[i].N) cs.push_back(coarse_slot(i, s, w[i].U[s], w[i].Go[s], cmode[i] == FM_COARSE_LEARNED));
+      FM_TRY(run_coarse_mixed(cs));
+      for (int i : ids)
+        if (s < prm[i].N) FM_HIP(copy_f64(w[i].U[s + 1], w[i].Go[s], (int64_t)inst[i].np * inst[i].np, st));
+    }
     std::vector<std::pair<int, int>> all;
-    for (int i = 0; i < batch; ++i)
-      if (prm[i].coarse == FM_COARSE_LEARNED)
+    for (int i : ids)
+      if (cmode[i] == FM_COARSE_LEARNED)
         for (int t = 0; t < prm[i].N; ++t) all.push_back({i, t});
-    FM_TRY(norms(all));
-    for (int i = 0; i < batch; ++i) {
-      if (prm[i].coarse != FM_COARSE_LEARNED) continue;
+    if (all.empty()) return FM_OK;
+    FM_TRY(nonfinite(all));
+    for (int i : ids) {
+      if (cmode[i] != FM_COARSE_LEARNED) continue;
       int first_bad = -1;
       for (int t = 0; t < prm[i].N && first_bad < 0; ++t)
-        if (!std::isfinite(hredu[(size_t)t * batch + i])) first_bad = t;
+        if (hredu[(size_t)t * batch + i] != 0.0) first_bad = t;
       if (first_bad < 0) continue;
       for (int t = first_bad; t < prm[i].N; ++t) {
         std::vector<CoarseSlot> one(1, coarse_slot(i, t, w[i].U[t], w[i].Go[t], true));
         FM_TRY(run_coarse(one, prm[i].coarse_steps, st));
-        FM_TRY(norms({{i, t}}));
-        if (!std::isfinite(hredu[(size_t)t * batch + i])) {
-          w[i].use_learned[t] = 0;
+        FM_TRY(nonfinite({{i, t}}));
+        w[i].use_learned[t] = hredu[(size_t)t * batch + i] == 0.0;
+        if (!w[i].use_learned[t]) {
           one[0] = coarse_slot(i, t, w[i].U[t], w[i].Go[t], false);
           FM_TRY(run_coarse(one, prm[i].coarse_steps, st));
         }
         FM_HIP(copy_f64(w[i].U[t + 1], w[i].Go[t], (int64_t)inst[i].np * inst[i].np, st));
       }
     }
+    return FM_OK;
+  };
+  {
+    std::vector<int> ids(batch);
+    for (int i = 0; i < batch; ++i) ids[i] = i;
+    FM_TRY(step0(ids));
   }
 
-  // ---- iterations
-  std::vector<int> live(batch, 0), iters(batch, 0);
+  // ---- iterations (each problem counts its own: kk[i] iterations done)
+  std::vector<int> live(batch, 0), kk(batch, 0), restarts(batch, 0);
   std::vector<fm_status> ist(batch, FM_OK);
   std::vector<double> lastinc(batch, 0.0);
   std::vector<std::vector<double>> hist(batch);
@@ -849,20 +995,25 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
   FM_TRY(ensure_part(npairs * nblk * 3 + npairs * 3 + npairs * 2));
   double* d_red = part + npairs * nblk * 3;
   double* d_cand = d_red + npairs * 3;  // defects of the learned / Euler candidates
-  FM_TRY(ensure_hredu(npairs * 3));
 
-  for (int k = 0;; ++k) {
+  for (int round = 0;; ++round) {
     bool any = false;
-    for (int i = 0; i < batch; ++i) any |= live[i] != 0;
+    int kmin = Nmax;
+    for (int i = 0; i < batch; ++i)
+      if (live[i]) {
+        any = true;
+        kmin = std::min(kmin, kk[i]);
+      }
     if (!any) break;
     FM_HIP(hipStreamSynchronize(st));
     ring.reset();
-    // fine solves of all live (problem, slice >= k) pairs in one launch per product
+    // fine solves of all live (problem, slice >= k) pairs in one launch per product;
+    // slices below k are already the serial fine solution
     std::vector<FineSlot> fs;
     std::vector<PrepItem> prep;
-    for (int s = k; s < Nmax; ++s)
+    for (int s = kmin; s < Nmax; ++s)
       for (int i = 0; i < batch; ++i) {
-        if (!live[i] || s >= prm[i].N) continue;
+        if (!live[i] || s >= prm[i].N || s < kk[i]) continue;
         const int N = prm[i].N;
         const double ta = s * prm[i].T / N, tb = (s + 1) * prm[i].T / N;
         FineSlot f{i, w[i].Fo[s], w[i].ya[s], w[i].yb[s], w[i].p[s], w[i].kacc[s], (tb - ta) / prm[i].fine_steps};
@@ -874,7 +1025,6 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
       FM_TRY(push(prep.data(), prep.size() * sizeof(PrepItem), &d, st));
       FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), dt, nullptr, st));
     }
-    // all live problems share fine_steps per call: group by step count
     {
       std::map<int, std::vector<FineSlot>> by;
       for (auto& f : fs) by[prm[f.inst].fine_steps].push_back(f);
@@ -888,9 +1038,9 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
       std::vector<CoarseSlot> ce, cl;
       std::vector<std::pair<int, int>> cl_is;  // (problem, slice) of each candidate
       std::vector<DotItem> di;
-      for (int s = k; s < Nmax; ++s)
+      for (int s = kmin; s < Nmax; ++s)
         for (int i = 0; i < batch; ++i) {
-          if (!live[i] || s >= prm[i].N || prm[i].coarse != FM_COARSE_LEARNED) continue;
+          if (!live[i] || s >= prm[i].N || s < kk[i] || cmode[i] != FM_COARSE_LEARNED) continue;
           CoarseSlot c = coarse_slot(i, s, w[i].U[s], w[i].Go[s], false);
           c.y0 = w[i].ya[s];
           c.y1 = w[i].yb[s];
@@ -925,26 +1075,27 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
             FM_HIP(copy_f64(w[i].Go[s2], w[i].gl[s2], (int64_t)inst[i].np * inst[i].np, st));
         }
         for (int i = 0; i < batch; ++i)
-          if (live[i] && prm[i].coarse == FM_COARSE_LEARNED) {
+          if (live[i] && cmode[i] == FM_COARSE_LEARNED) {
             int c2 = 0;
-            for (int s2 = k; s2 < prm[i].N; ++s2) c2 += w[i].use_learned[s2];
+            for (int s2 = kk[i]; s2 < prm[i].N; ++s2) c2 += w[i].use_learned[s2];
             learned_count[i] = c2;
           }
       }
     }
-    // sequential correction sweep
-    for (int s = k; s < Nmax; ++s) {
+    // sequential correction sweep: U^{k+1}_{n+1} = G(U^{k+1}_n) + F(U^k_n) - G(U^k_n);
+    // at n = k both coarse values are of the exact slice, so U^{k+1}_{k+1} = F(U^k_k)
+    for (int s = kmin; s < Nmax; ++s) {
       std::vector<CoarseSlot> cs;
       std::vector<CorrItem> ci;
       for (int i = 0; i < batch; ++i) {
-        if (!live[i] || s >= prm[i].N) continue;
-        if (s > k)
+        if (!live[i] || s >= prm[i].N || s < kk[i]) continue;
+        if (s > kk[i])
           cs.push_back(coarse_slot(i, s, w[i].U[s], w[i].gnew,
-                                   prm[i].coarse == FM_COARSE_LEARNED && w[i].use_learned[s]));
+                                   cmode[i] == FM_COARSE_LEARNED && w[i].use_learned[s]));
         CorrItem c;
         c.u = w[i].U[s + 1];
         c.f = w[i].Fo[s];
-        c.gnew = (s > k) ? w[i].gnew : w[i].Go[s];
+        c.gnew = (s > kk[i]) ? w[i].gnew : w[i].Go[s];
         c.gold = w[i].Go[s];
         c.count = (int64_t)inst[i].np * inst[i].np;
         c.inst = i;
@@ -962,11 +1113,12 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
     FM_HIP(hipMemcpyAsync(hredu, d_red, npairs * 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     FM_HIP(hipStreamSynchronize(st));
     if (timing) FM_TRY(collect_timing());
+    std::vector<int> restart;
     for (int i = 0; i < batch; ++i) {
       if (!live[i]) continue;
       double inc = 0.0;
       bool bad = false;
-      for (int s = k; s < prm[i].N; ++s) {
+      for (int s = kk[i]; s < prm[i].N; ++s) {
         const double* r = hredu + ((size_t)s * batch + i) * 3;
         const double d = r[0] > 0 ? std::sqrt(r[0]) : 0.0;
         const double u = r[1] > 0 ? std::sqrt(r[1]) : 0.0;
@@ -975,34 +1127,45 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
         inc = std::max(inc, q);
         if (r[2] != 0.0) bad = true;
       }
-      iters[i] = k + 1;
+      kk[i]++;
       lastinc[i] = inc;
       hist[i].push_back(inc);
       if (bad) {
-        ist[i] = FM_ERR_NONFINITE;
-        live[i] = 0;
+        if (cmode[i] == FM_COARSE_LEARNED) {
+          // the learned step diverged in a sweep: restart with Euler
+          cmode[i] = FM_COARSE_EULER;
+          learned_count[i] = 0;
+          restarts[i]++;
+          kk[i] = 0;
+          restart.push_back(i);
+        } else {
+          ist[i] = FM_ERR_NONFINITE;
+          live[i] = 0;
+        }
         continue;
       }
-      if (inc <= prm[i].tol || k + 1 >= prm[i].N) {
+      if (inc <= prm[i].tol || kk[i] >= prm[i].N) {
         live[i] = 0;
-      } else if (k + 1 >= prm[i].max_iter) {
+      } else if (kk[i] >= prm[i].max_iter) {
         live[i] = 0;
         ist[i] = FM_WARN_NOT_CONVERGED;
       }
     }
+    if (!restart.empty()) FM_TRY(step0(restart));
     if (verbose) {
       double worst = 0.0;
       int nlive = 0;
       for (int i = 0; i < batch; ++i) {
-        if (iters[i] == k + 1) worst = std::max(worst, lastinc[i]);
+        if (live[i] || kk[i] > 0) worst = std::max(worst, lastinc[i]);
         nlive += live[i];
       }
       const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-      fprintf(stderr, "[fm] iteration %d: max increment %.3e, %d problems still iterating, %.2f s\n", k + 1, worst,
-              nlive, sec);
+      fprintf(stderr, "[fm] round %d: max increment %.3e, %d problems still iterating, %.2f s\n", round + 1,
+              worst, nlive, sec);
       fflush(stderr);
     }
   }
+  std::vector<int> iters = kk;
 
   // ---- result, residual and refinement
   std::vector<double*> X(batch);
@@ -1019,6 +1182,7 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
       for (size_t j = 0; j < hist[i].size() && j < 64; ++j) stats[i].hist[j] = hist[i][j];
       stats[i].residual_before = stats[i].residual = NAN;
       stats[i].learned_slices = learned_count[i];
+      stats[i].learned_restarts = restarts[i];
       stats[i].fine_launches = (int32_t)t_launches;
       stats[i].fine_ms = t_ms;
       stats[i].fine_flops = t_flops;
@@ -1365,11 +1529,11 @@ fm_status Flow::ensure_moments(hipStream_t st) {
 }
 
 fm_status Flow::learned_table(const std::vector<CoefRow>& rows, double* coef, hipStream_t st) {
+  if (rows.empty()) return FM_OK;
   if (!model.loaded) {
     set_error("learned coarse step requested but no coarse model is loaded");
     return FM_ERR_INVALID;
   }
-  if (rows.empty()) return FM_OK;
   FM_TRY(ensure_moments(st));
   const int64_t S = (int64_t)rows.size();
   std::vector<float> X(S * 6);

@@ -116,6 +116,7 @@ struct Flow {
   std::vector<Inst> inst;
   Model model;
   bool autotune = true;
+  int force_bm = 0, force_bk = 0;  // option tile=<bm>x<bk>: fixed product tile (flow dtype)
   std::string autotune_cache;
   Ring ring;
   Arena work;      // parareal workspace

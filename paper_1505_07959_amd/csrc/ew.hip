@@ -56,6 +56,12 @@ __global__ void k_prep(const PrepItem* __restrict__ items, const int* __restrict
   }
 }
 
+template <class T>
+__global__ void k_fill(T* __restrict__ dst, int64_t count) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = cvt<T>(0.25 + 0.001 * (double)((e * 2654435761ll) % 1000));
+}
+
 __global__ void k_identity(double* __restrict__ dst, int n, int np) {
   const int64_t total = (int64_t)np * np;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -180,7 +186,10 @@ __global__ void k_dots_part(const DotItem* __restrict__ items, double* __restric
   __shared__ double sh[EW_THREADS];
   const DotItem it = items[blockIdx.y];
   double s = 0.0;
-  if (it.sub) {
+  if (it.mode == 1) {
+    for (int64_t e = blockIdx.x * (int64_t)EW_THREADS + threadIdx.x; e < it.count; e += (int64_t)gridDim.x * EW_THREADS)
+      s += isfinite(it.a[e]) ? 0.0 : 1.0;
+  } else if (it.sub) {
     for (int64_t e = blockIdx.x * (int64_t)EW_THREADS + threadIdx.x; e < it.count; e += (int64_t)gridDim.x * EW_THREADS)
       s += (it.a[e] - it.sub[e]) * (it.b[e] - it.sub[e]);
   } else {
@@ -285,6 +294,18 @@ hipError_t convert_f64(void* dst, int dt, const double* src, double shift, int n
     case DT_F32: hipLaunchKernelGGL(k_convert<float>, g, b, 0, st, (float*)dst, src, shift, n, np); break;
     case DT_BF16: hipLaunchKernelGGL(k_convert<__bf16>, g, b, 0, st, (__bf16*)dst, src, shift, n, np); break;
     case DT_F16: hipLaunchKernelGGL(k_convert<_Float16>, g, b, 0, st, (_Float16*)dst, src, shift, n, np); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t fill_pattern(void* dst, int dt, int64_t count, hipStream_t st) {
+  dim3 g(ew_grid(count)), b(EW_THREADS);
+  switch (dt) {
+    case DT_F64: hipLaunchKernelGGL(k_fill<double>, g, b, 0, st, (double*)dst, count); break;
+    case DT_F32: hipLaunchKernelGGL(k_fill<float>, g, b, 0, st, (float*)dst, count); break;
+    case DT_BF16: hipLaunchKernelGGL(k_fill<__bf16>, g, b, 0, st, (__bf16*)dst, count); break;
+    case DT_F16: hipLaunchKernelGGL(k_fill<_Float16>, g, b, 0, st, (_Float16*)dst, count); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace fm {
 
 // Product arithmetic (same numbering as fm_dtype in include/fm.h).
@@ -72,6 +74,9 @@ struct GemmCfg {
 hipError_t launch_gemm(const GemmCfg& cfg, int epi, const GItem* items, const int* tile_start,
                        int nitems, int total_tiles, int grid, const int* live, hipStream_t st);
 
+// All compiled tile configurations for a dtype (first = default).
+std::vector<GemmCfg> gemm_configs(int dt);
+
 // Number of workgroups a persistent launch of `cfg` should use (all tiles
 // resident at most once): CUs * resident WGs per CU.
 int gemm_max_grid(const GemmCfg& cfg);
@@ -81,6 +86,8 @@ int gemm_max_grid(const GemmCfg& cfg);
 hipError_t stage_pad_f64(double* dst, int np, const double* src, int64_t n, int64_t ld, hipStream_t st);
 // dst(op dtype, np x np) <- src(FP64) + shift*I (shift only on the leading n x n diagonal)
 hipError_t convert_f64(void* dst, int dt, const double* src, double shift, int n, int np, hipStream_t st);
+// dst (count elements of dtype dt) <- a fixed non-trivial pattern (for timing)
+hipError_t fill_pattern(void* dst, int dt, int64_t count, hipStream_t st);
 // dst(FP64 np x np) <- identity on the leading n x n block
 hipError_t set_identity(double* dst, int n, int np, hipStream_t st);
 // dst(FP64, np x np) <- src (n x n, ld n) padded ; or unpad dst(n x n) <- src(np)
@@ -132,7 +139,7 @@ struct DotItem {
   const double* b;
   int64_t count;
   int slot;
-  int pad_;
+  int mode;           // 0: dot product; 1: number of non-finite entries of a
   const double* sub;  // when non-null: <a - sub, b - sub>
 };
 hipError_t launch_dots(const DotItem* items, int nitems, double* part, int nblk, double* out, hipStream_t st);

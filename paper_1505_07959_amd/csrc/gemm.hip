@@ -162,7 +162,7 @@ __device__ __forceinline__ void epilogue(const GItem& it, int n, int64_t idx, bo
 }
 
 template <int DT, int BM, int BK, int EPI>
-__global__ __launch_bounds__(256) void gemm_kernel(const GItem* __restrict__ items,
+__global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 : 1) void gemm_kernel(const GItem* __restrict__ items,
                                                    const int* __restrict__ tile_start, int nitems,
                                                    int total_tiles, const int* __restrict__ live) {
   using TR = Tr<DT>;
@@ -365,12 +365,17 @@ int occupancy_cfg() {
 // Supported configurations: bm in {64, 128}; bk per dtype.
 #define FM_CFG_LIST(X) \
   X(DT_F64, 128, 16)   \
+  X(DT_F64, 128, 32)   \
   X(DT_F64, 64, 16)    \
+  X(DT_F64, 64, 32)    \
   X(DT_F32, 128, 32)   \
+  X(DT_F32, 128, 16)   \
   X(DT_F32, 64, 32)    \
   X(DT_BF16, 128, 64)  \
+  X(DT_BF16, 128, 32)  \
   X(DT_BF16, 64, 64)   \
   X(DT_F16, 128, 64)   \
+  X(DT_F16, 128, 32)   \
   X(DT_F16, 64, 64)
 
 hipError_t launch_gemm(const GemmCfg& cfg, int epi, const GItem* items, const int* tile_start, int nitems,
@@ -384,6 +389,15 @@ hipError_t launch_gemm(const GemmCfg& cfg, int epi, const GItem* items, const in
   FM_CFG_LIST(FM_DISPATCH)
 #undef FM_DISPATCH
   return hipErrorInvalidValue;
+}
+
+std::vector<GemmCfg> gemm_configs(int dt) {
+  std::vector<GemmCfg> v;
+#define FM_LIST(D, M, K) \
+  if (dt == D) v.push_back(GemmCfg{D, M, K});
+  FM_CFG_LIST(FM_LIST)
+#undef FM_LIST
+  return v;
 }
 
 int gemm_max_grid(const GemmCfg& cfg) {

@@ -51,14 +51,14 @@ class fm_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("learned_slices", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("increment", ctypes.c_double), ("residual_before", ctypes.c_double),
                 ("residual", ctypes.c_double), ("hist", ctypes.c_double * 64),
-                ("fine_launches", ctypes.c_int32), ("reserved_", ctypes.c_int32), ("fine_ms", ctypes.c_double),
+                ("fine_launches", ctypes.c_int32), ("learned_restarts", ctypes.c_int32), ("fine_ms", ctypes.c_double),
                 ("fine_flops", ctypes.c_double), ("fine_phase_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {"iters": self.iters, "refine_steps": self.refine_steps, "learned_slices": self.learned_slices,
                 "status": self.status, "increment": self.increment, "residual_before": self.residual_before,
                 "residual": self.residual, "hist": list(self.hist[:max(0, min(self.iters, 64))]),
-                "fine_launches": self.fine_launches, "fine_ms": self.fine_ms, "fine_flops": self.fine_flops,
+                "fine_launches": self.fine_launches, "learned_restarts": self.learned_restarts, "fine_ms": self.fine_ms, "fine_flops": self.fine_flops,
                 "fine_phase_ms": self.fine_phase_ms}
 
 

@@ -120,7 +120,7 @@ def test_features_match_oracle(kind):
 
 
 @pytest.mark.parametrize("kind,T,N,S,dtype,bar", [(HOMOTOPY, 1.0, 16, 8, "f64", 1e-10),
-                                                   (STEADY_INV, 24.0, 16, 8, "f64", 1e-10),
+                                                   (STEADY_INV, 12.0, 32, 8, "f64", 1e-10),
                                                    (HOMOTOPY, 1.0, 16, 8, "f32", 1e-5)])
 def test_learned_parareal_matches_oracle(kind, T, N, S, dtype, bar):
     """A network whose output is its last bias (exact in FP32): both sides use
@@ -130,7 +130,9 @@ def test_learned_parareal_matches_oracle(kind, T, N, S, dtype, bar):
     A, Q, lam = inputs.spd(n, "loguniform", 1e-2, 10.0, 51) if kind == HOMOTOPY else \
         inputs.spd(n, "loguniform", 1e-3, 1.0, 52, scale_to_unit=True)
     theta = np.zeros(9288)
-    b4 = np.array([0.0, 0.0, 0.5, -0.5, 0.0, 0.0, 0.0, 0.0])   # towards the Taylor member
+    # towards the Taylor member of the homotopy step; small for the steady flow
+    b4 = np.array([0.0, 0.0, 0.5, -0.5, 0.0, 0.0, 0.0, 0.0]) if kind == HOMOTOPY else \
+        np.array([0.0, 0.0, 0.125, -0.03125, 0.0, 0.0, 0.0, 0.0])
     theta[-8:] = b4
     norm = np.concatenate([np.zeros(6), np.ones(6)])
     salg = SpectralAlgebra(Q, lam)
@@ -147,6 +149,7 @@ def test_learned_parareal_matches_oracle(kind, T, N, S, dtype, bar):
     e = rel(host(out), salg.to_matrix(ref["U"][-1]))
     say("learned parareal kind %d %s: iters %d, learned slices %d (oracle %d), rel err %.2e" %
         (kind, dtype, stats[0]["iters"], stats[0]["learned_slices"], sum(ref["choices"][-1]), e))
+    assert stats[0]["learned_restarts"] == 0
     np.testing.assert_allclose(stats[0]["hist"], ref["increments"], rtol=1e-3 if dtype == "f32" else 1e-6)
     assert e <= bar
 
@@ -169,8 +172,15 @@ def test_training_pipeline_small(tmp_path):
     flow = fm.fm_flow_create([(HOMOTOPY, dev(A))], "f32", "coarse_model=" + path)
     try:
         out = empty(64)
-        st, stats = fm.fm_parareal_solve(flow, None, [out], [{"T": 1.0, "N": 16, "fine_steps": 8, "max_iter": 16,
-                                                              "tol": 1e-8, "coarse": fm.FM_COARSE_LEARNED}])
-        assert st == fm.FM_OK and stats[0]["iters"] < 16
+        its, rs = {}, {}
+        for coarse in (fm.FM_COARSE_EULER, fm.FM_COARSE_LEARNED):
+            st, stats = fm.fm_parareal_solve(flow, None, [out], [{"T": 1.0, "N": 32, "fine_steps": 8, "max_iter": 32,
+                                                                  "tol": 1e-8, "coarse": coarse}])
+            assert st == fm.FM_OK
+            its[coarse] = stats[0]["iters"]
+            rs[coarse] = stats[0]["learned_restarts"]
+        say("iterations to 1e-8: Euler %d, learned %d (restarts %d)" % (its[0], its[1], rs[1]))
+        # a weakly trained network either helps or is caught by the Euler fallback
+        assert its[fm.FM_COARSE_LEARNED] <= its[fm.FM_COARSE_EULER] or rs[fm.FM_COARSE_LEARNED] > 0
     finally:
         fm.fm_destroy(flow)
