@@ -142,12 +142,23 @@ Flow::~Flow() {
   for (auto& in : inst) {
     if (in.A64) (void)hipFree(in.A64);
     if (in.Bop) (void)hipFree(in.Bop);
+    if (in.B64) (void)hipFree(in.B64);
   }
   ring.release();
   work.release();
   prop.release();
   if (part) (void)hipFree(part);
   if (hredu) (void)hipHostFree(hredu);
+}
+
+fm_status Flow::pad_copy(const std::vector<double*>& dst, const std::vector<const double*>& src, int pad,
+                         hipStream_t st) {
+  std::vector<PadItem> it(batch);
+  for (int i = 0; i < batch; ++i) it[i] = PadItem{dst[i], src[i], inst[i].n, inst[i].np};
+  void* d = nullptr;
+  FM_TRY(push(it.data(), it.size() * sizeof(PadItem), &d, st));
+  FM_HIP(launch_pad_copy((const PadItem*)d, batch, pad, st));
+  return FM_OK;
 }
 
 fm_status Flow::ensure_part(size_t count) {
@@ -706,9 +717,17 @@ fm_status Flow::fine_propagate(double t1, double t0, int steps, const double* co
   }
   ring.reset();
   FM_HIP(hipStreamSynchronize(st));
+  {
+    std::vector<double*> dst(batch);
+    std::vector<const double*> src(batch);
+    for (int i = 0; i < batch; ++i) {
+      dst[i] = slots[i].x;
+      src[i] = xin[i];
+    }
+    FM_TRY(pad_copy(dst, src, 1, st));
+  }
   std::vector<PrepItem> prep;
   for (int i = 0; i < batch; ++i) {
-    FM_HIP(copy_in(slots[i].x, inst[i].np, xin[i], inst[i].n, st));
     PrepItem p{slots[i].x, nullptr, slots[i].ya, (int64_t)inst[i].np * inst[i].np, i, 0};
     prep.push_back(p);
   }
@@ -716,7 +735,15 @@ fm_status Flow::fine_propagate(double t1, double t0, int steps, const double* co
   FM_TRY(push(prep.data(), prep.size() * sizeof(PrepItem), &d, st));
   FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), dt, nullptr, st));
   FM_TRY(run_fine(slots, steps, st));
-  for (int i = 0; i < batch; ++i) FM_HIP(copy_out(xout[i], inst[i].n, slots[i].x, inst[i].np, st));
+  {
+    std::vector<double*> dst(batch);
+    std::vector<const double*> src(batch);
+    for (int i = 0; i < batch; ++i) {
+      dst[i] = xout[i];
+      src[i] = slots[i].x;
+    }
+    FM_TRY(pad_copy(dst, src, 0, st));
+  }
   return FM_OK;
 }
 
@@ -760,9 +787,17 @@ fm_status Flow::coarse_propagate(double t1, double t0, int steps, int coarse, co
   }
   ring.reset();
   FM_HIP(hipStreamSynchronize(st));
-  for (int i = 0; i < batch; ++i) FM_HIP(copy_in(slots[i].xout, inst[i].np, xin[i], inst[i].n, st));
+  std::vector<double*> pd(batch), od(batch);
+  std::vector<const double*> ps(batch), os(batch);
+  for (int i = 0; i < batch; ++i) {
+    pd[i] = slots[i].xout;
+    ps[i] = xin[i];
+    od[i] = xout[i];
+    os[i] = slots[i].xout;
+  }
+  FM_TRY(pad_copy(pd, ps, 1, st));
   FM_TRY(run_coarse(slots, steps, st));
-  for (int i = 0; i < batch; ++i) FM_HIP(copy_out(xout[i], inst[i].n, slots[i].xout, inst[i].np, st));
+  FM_TRY(pad_copy(od, os, 0, st));
   return FM_OK;
 }
 
@@ -1577,12 +1612,18 @@ fm_status Flow::features(double h, const double* const* X, const double* const* 
   std::vector<Buf> b(batch);
   double* part = nullptr;
   const int nblk = 16;
+  for (int i = 0; i < batch; ++i)
+    if (!inst[i].B64) {
+      FM_HIP(hipMalloc((void**)&inst[i].B64, (size_t)inst[i].np * inst[i].np * 8));
+      FM_HIP(convert_f64(inst[i].B64, DT_F64, inst[i].A64, inst[i].kind == FM_FLOW_INV_HOMOTOPY ? -1.0 : 0.0,
+                         inst[i].n, inst[i].np, st));
+    }
   for (int pass = 0; pass < 2; ++pass) {
     prop.measuring = (pass == 0);
     prop.used = 0;
     for (int i = 0; i < batch; ++i) {
       const size_t np2 = (size_t)inst[i].np * inst[i].np * 8;
-      b[i].B = (double*)prop.take(np2);
+      b[i].B = inst[i].B64;
       b[i].x = (double*)prop.take(np2);
       b[i].f = (double*)prop.take(np2);
       for (int q = 0; q < 3; ++q) {
@@ -1598,12 +1639,18 @@ fm_status Flow::features(double h, const double* const* X, const double* const* 
   }
   ring.reset();
   std::vector<int> ii(batch);
-  for (int i = 0; i < batch; ++i) {
-    ii[i] = i;
-    FM_HIP(convert_f64(b[i].B, DT_F64, inst[i].A64, inst[i].kind == FM_FLOW_INV_HOMOTOPY ? -1.0 : 0.0, inst[i].n,
-                       inst[i].np, st));
-    FM_HIP(copy_in(b[i].x, inst[i].np, X[i], inst[i].n, st));
-    FM_HIP(copy_in(b[i].f, inst[i].np, FX[i], inst[i].n, st));
+  {
+    std::vector<double*> dx(batch), df(batch);
+    std::vector<const double*> sx(batch), sf(batch);
+    for (int i = 0; i < batch; ++i) {
+      ii[i] = i;
+      dx[i] = b[i].x;
+      sx[i] = X[i];
+      df[i] = b[i].f;
+      sf[i] = FX[i];
+    }
+    FM_TRY(pad_copy(dx, sx, 1, st));
+    FM_TRY(pad_copy(df, sf, 1, st));
   }
   auto prod = [&](int which, double scale) -> fm_status {
     std::vector<GItem> it;

@@ -79,6 +79,7 @@ struct Inst {
   GemmCfg cfg64{};   // FP64 config (residual / refinement)
   double* A64 = nullptr;  // padded FP64 A
   void* Bop = nullptr;    // right operand of the first product: A - I (homotopy) or A
+  double* B64 = nullptr;  // the same in FP64 (learned-step features; made on first use)
   double mu[4] = {0, 0, 0, 0};  // tr((A - I)^j) / n
 };
 
@@ -148,6 +149,9 @@ struct Flow {
   // make sure `bytes` of item lists can be pushed without an intermediate reset
   fm_status reserve_ring(size_t bytes, hipStream_t st);
   fm_status ensure_part(size_t count);
+  // batched zero-padded copies in (pad = 1) or out (pad = 0) of the library layout
+  fm_status pad_copy(const std::vector<double*>& dst, const std::vector<const double*>& src, int pad,
+                     hipStream_t st);
   fm_status ensure_hredu(size_t count);
 
   fm_status run_fine(const std::vector<FineSlot>& slots, int steps, hipStream_t st);

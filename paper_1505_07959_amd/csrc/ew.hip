@@ -86,6 +86,23 @@ __global__ void k_copy_out(double* __restrict__ dst, int n, const double* __rest
   }
 }
 
+__global__ void k_pad_copy(const PadItem* __restrict__ items, int pad) {
+  const PadItem it = items[blockIdx.y];
+  if (pad) {
+    const int64_t total = (int64_t)it.np * it.np;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t i = e / it.np, j = e % it.np;
+      it.dst[e] = (i < it.n && j < it.n) ? it.src[i * it.n + j] : 0.0;
+    }
+  } else {
+    const int64_t total = (int64_t)it.n * it.n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t i = e / it.n, j = e % it.n;
+      it.dst[e] = it.src[i * it.np + j];
+    }
+  }
+}
+
 __global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, int64_t count) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
     dst[e] = src[e];
@@ -323,6 +340,12 @@ hipError_t copy_in(double* dst, int np, const double* src, int n, hipStream_t st
 
 hipError_t copy_out(double* dst, int n, const double* src, int np, hipStream_t st) {
   hipLaunchKernelGGL(k_copy_out, dim3(ew_grid((int64_t)n * n)), dim3(EW_THREADS), 0, st, dst, n, src, np);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_copy(const PadItem* items, int nitems, int pad, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pad_copy, dim3(64, nitems), dim3(EW_THREADS), 0, st, items, pad);
   return hipGetLastError();
 }
 

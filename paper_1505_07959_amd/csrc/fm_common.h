@@ -94,6 +94,15 @@ hipError_t set_identity(double* dst, int n, int np, hipStream_t st);
 hipError_t copy_in(double* dst, int np, const double* src, int n, hipStream_t st);
 hipError_t copy_out(double* dst, int n, const double* src, int np, hipStream_t st);
 hipError_t copy_f64(double* dst, const double* src, int64_t count, hipStream_t st);
+// Batched copies between n x n (leading dimension n) and padded np x np FP64
+// matrices: pad = 1: dst(np) <- src(n) zero padded; pad = 0: dst(n) <- src(np).
+struct PadItem {
+  double* dst;
+  const double* src;
+  int n;
+  int np;
+};
+hipError_t launch_pad_copy(const PadItem* items, int nitems, int pad, hipStream_t st);
 
 // Batched parareal correction: for each item j: U1 <- F + (Gnew - Gold); Gold <- Gnew;
 // partial sums of ||U1 - Uold||^2 and ||U1||^2 (Uold read from U1 before the write)
