@@ -133,7 +133,9 @@ typedef struct {
  * timing=0|1 (default 0: fill the timing fields of fm_stats), verbose=0|1
  * (one stderr line per parareal iteration), tile=<bm>x<bk> (fixed product
  * tile instead of the autotuned one; ignored where it does not divide the
- * padded order).  Tile shapes never change results, only speed.
+ * padded order), graph=0|1 (default 1: the launches of one RK4 step of a
+ * fine phase are captured in a hipGraph and replayed for every step; off
+ * while timing=1).  Tile shapes and graphs never change results.
  * out: host; receives the handle.  Returns FM_ERR_INVALID for batch < 1,
  * n out of range, lda < n, an unknown kind/dtype or a NULL A.
  */

@@ -135,7 +135,19 @@ fm_status Flow::collect_timing() {
   return FM_OK;
 }
 
+void Flow::release_graphs() {
+  for (auto q : pending_stream) (void)hipStreamSynchronize(q);
+  pending_stream.clear();
+  for (auto g : pending_exec) (void)hipGraphExecDestroy(g);
+  for (auto g : pending_graph) (void)hipGraphDestroy(g);
+  pending_exec.clear();
+  pending_graph.clear();
+}
+
 Flow::~Flow() {
+  (void)hipDeviceSynchronize();
+  release_graphs();
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
   for (auto e : ev) (void)hipEventDestroy(e);
   if (model.d_theta) (void)hipFree(model.d_theta);
   if (model.d_norm) (void)hipFree(model.d_norm);
@@ -343,6 +355,8 @@ fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char*
   if (kv.count("autotune_cache")) autotune_cache = kv["autotune_cache"];
   if (kv.count("timing")) timing = kv["timing"] != "0";
   if (kv.count("verbose")) verbose = kv["verbose"] != "0";
+  if (kv.count("graph")) use_graph = kv["graph"] != "0";
+  if (use_graph) FM_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
   if (kv.count("tile") && sscanf(kv["tile"].c_str(), "%dx%d", &force_bm, &force_bk) != 2) {
     set_error("option tile must read <bm>x<bk>");
     return FM_ERR_INVALID;
@@ -480,6 +494,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
     const int* ts;
     int n;
     int total;
+    int grid;
     double flops;  // algorithmic: 2 n^3 per item (unpadded order)
   };
   std::vector<Launch> seq;
@@ -522,6 +537,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
       L.ts = (const int*)dts;
       L.n = (int)sub.size();
       L.total = total;
+      L.grid = std::min(total, gemm_max_grid(L.cfg));
       seq.push_back(L);
     }
     return FM_OK;
@@ -537,6 +553,29 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
     if (!e0 || !e1) timing = false;
     else FM_HIP(hipEventRecord(e0, st));
   }
+  if (use_graph && cap_stream && !timing && steps > 1) {
+    // capture the launches of one RK4 step once, replay the graph `steps` times
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    FM_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (const Launch& L : seq) {
+      e = launch_gemm(L.cfg, L.epi, L.items, L.ts, L.n, L.total, L.grid, nullptr, cap_stream);
+      if (e != hipSuccess) break;
+    }
+    hipError_t e2 = hipStreamEndCapture(cap_stream, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_status(e, "fine-step graph capture");
+    }
+    pending_graph.push_back(g);
+    pending_exec.push_back(ge);
+    pending_stream.push_back(st);
+    for (int step = 0; step < steps; ++step) FM_HIP(hipGraphLaunch(ge, st));
+    return FM_OK;
+  }
   for (int step = 0; step < steps; ++step)
     for (const Launch& L : seq) {
       const bool rec = timing && L.epi == EPI_RK4;
@@ -547,8 +586,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
         if (a && b) FM_HIP(hipEventRecord(a, st));
         else idx = -1;
       }
-      FM_HIP(launch_gemm(L.cfg, L.epi, L.items, L.ts, L.n, L.total, std::min(L.total, gemm_max_grid(L.cfg)),
-                         nullptr, st));
+      FM_HIP(launch_gemm(L.cfg, L.epi, L.items, L.ts, L.n, L.total, L.grid, nullptr, st));
       if (idx >= 0) {
         FM_HIP(hipEventRecord(ev[idx + 1], st));
         ev_pairs.push_back({idx, L.flops});
@@ -715,8 +753,9 @@ fm_status Flow::fine_propagate(double t1, double t0, int steps, const double* co
     }
     if (pass == 0) FM_TRY(prop.reserve(prop.used));
   }
-  ring.reset();
   FM_HIP(hipStreamSynchronize(st));
+  release_graphs();
+  ring.reset();
   {
     std::vector<double*> dst(batch);
     std::vector<const double*> src(batch);
@@ -1041,6 +1080,7 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
       }
     if (!any) break;
     FM_HIP(hipStreamSynchronize(st));
+    release_graphs();
     ring.reset();
     // fine solves of all live (problem, slice >= k) pairs in one launch per product;
     // slices below k are already the serial fine solution

@@ -130,6 +130,12 @@ struct Flow {
   // optional HIP-event timing of the fine propagator (option timing=1)
   bool timing = false;
   bool verbose = false;  // option verbose=1: one stderr line per parareal iteration
+  bool use_graph = true; // option graph=0|1: replay the RK4 step of a fine phase from a hipGraph
+  hipStream_t cap_stream = nullptr;          // capture stream (default priority)
+  std::vector<hipGraphExec_t> pending_exec;  // executable graphs kept until the next synchronisation
+  std::vector<hipGraph_t> pending_graph;
+  std::vector<hipStream_t> pending_stream;  // stream each pending graph was launched on
+  void release_graphs();
   std::vector<hipEvent_t> ev;      // event pool
   size_t ev_used = 0;
   std::vector<std::pair<int, double>> ev_pairs;  // (index of start event, flops) of RK4-epilogue launches

@@ -5,7 +5,8 @@
 //
 // Design (CDNA4):
 //  * 256 threads = 4 wavefronts in a 2 x 2 grid; each wave owns a
-//    (BM/2) x (BM/2) block of C built from MFMA tiles:
+//    (BM/2) x (BM/2) block of C built from MFMA tiles (BM = 256 for the
+//    16-bit types: 128 x 128 per wave halves LDS and L2 traffic per flop):
 //      FP64  v_mfma_f64_16x16x4f64     (16x16 blocks, FP64 accumulate)
 //      FP32  v_mfma_f32_32x32x2f32     (32x32 blocks)
 //      BF16  v_mfma_f32_32x32x16_bf16  (32x32 blocks, FP32 accumulate)
@@ -29,6 +30,10 @@
 //  * No atomics and a fixed reduction order: the kernels are deterministic,
 //    which the parareal exactness property relies on.
 #include "fm_common.h"
+
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace fm {
 namespace {
@@ -323,7 +328,10 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
 #pragma unroll
     for (int i = 0; i < RM; ++i)
 #pragma unroll
-      for (int j = 0; j < RN; ++j)
+      for (int j = 0; j < RN; ++j) {
+        // one MFMA block at a time: keeps the epilogue's loads from being
+        // hoisted all together (register pressure of the 256-wide tiles)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int v = 0; v < NACC; ++v) {
           int r, c;
@@ -333,6 +341,7 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
           const int64_t idx = (int64_t)gr * np + gc;
           epilogue<DT, EPI>(it, n_valid, idx, gr == gc && gr < n_valid, (double)acc[i][j][v]);
         }
+      }
   }
 }
 
@@ -373,9 +382,13 @@ int occupancy_cfg() {
   X(DT_F32, 64, 32)    \
   X(DT_BF16, 128, 64)  \
   X(DT_BF16, 128, 32)  \
+  X(DT_BF16, 256, 32)  \
+  X(DT_BF16, 256, 64)  \
   X(DT_BF16, 64, 64)   \
   X(DT_F16, 128, 64)   \
   X(DT_F16, 128, 32)   \
+  X(DT_F16, 256, 32)   \
+  X(DT_F16, 256, 64)   \
   X(DT_F16, 64, 64)
 
 hipError_t launch_gemm(const GemmCfg& cfg, int epi, const GItem* items, const int* tile_start, int nitems,
@@ -401,14 +414,23 @@ std::vector<GemmCfg> gemm_configs(int dt) {
 }
 
 int gemm_max_grid(const GemmCfg& cfg) {
-  int dev = 0, cus = 0;
+  // queried once per (device, configuration), then served from a table
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int>, int> cache;
+  int dev = 0;
   (void)hipGetDevice(&dev);
+  const auto key = std::make_tuple(dev, cfg.dt, cfg.bm, cfg.bk);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
   int occ = 1;
 #define FM_OCC(D, M, K) \
   if (cfg.dt == D && cfg.bm == M && cfg.bk == K) occ = occupancy_cfg<D, M, K>();
   FM_CFG_LIST(FM_OCC)
 #undef FM_OCC
+  cache[key] = cus * occ;
   return cus * occ;
 }
 
