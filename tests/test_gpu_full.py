@@ -65,7 +65,9 @@ def test_large_homotopy_full_size(dtype, bar, K):
     say("  iters %d, sampled rel err %.2e, increment %.3e (oracle %.3e)" %
         (s["iters"], e, s["hist"][0], ref["increments"][0]))
     assert s["iters"] == K and e <= bar
-    assert abs(s["hist"][0] - ref["increments"][0]) <= 1e-6 * ref["increments"][0]
+    # the increment is a norm of differences of computed iterates: FP64 to 1e-6
+    # relative, FP32 to the rounding of its products
+    assert abs(s["hist"][0] - ref["increments"][0]) <= (1e-6 if dtype == "f64" else 1e-4) * ref["increments"][0]
 
 
 def test_steady_fp16_full_size():
