@@ -32,9 +32,11 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def traffic_for(kernel_key):
-    """HBM bytes per launch measured with rocprofv3 counters, if the kernel
-    source is unchanged since they were taken (else None)."""
+def traffic_for(kernel_key, items_per_launch):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE counters
+    recorded in profiles/traffic.json (bytes per slice product, calibrated
+    against a copy kernel of known size), scaled to this run's products per
+    launch; None when the GEMM source changed since the counters were taken."""
     try:
         data = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -45,7 +47,7 @@ def traffic_for(kernel_key):
     src = open(os.path.join(ROOT, "paper_1505_07959_amd", "csrc", "gemm.hip"), "rb").read()
     if hashlib.sha256(src).hexdigest() != ent.get("gemm_sha256"):
         return None
-    return ent.get("bytes_per_launch")
+    return ent["bytes_per_item"] * items_per_launch
 
 
 def cpu_baseline(A, n, fine_steps_total, coarse_steps_total, sample_steps):
@@ -78,7 +80,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--dtype", default="f64", choices=["f32", "f64", "bf16", "f16"])
     ap.add_argument("--tile", default=None, help="fixed product tile <bm>x<bk> instead of the autotuned one")
     ap.add_argument("--n", type=int, default=4096)
@@ -169,7 +171,8 @@ def main():
                    "iterations": iters, "converged": converged,
                    "fine_tflops_whole_solve": total_fine_flops / (elapsed / args.steps) / 1e12},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.dtype], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK[args.dtype], "traffic": traffic_for(key),
+                     "frac": achieved / PEAK[args.dtype],
+                     "traffic": traffic_for(key, flops_per_launch / (2.0 * n ** 3)),
                      "kernel": "gemm_kernel RK4-epilogue (fine propagator), avg of %d launches, %.3e flop/launch"
                                % (s["fine_launches"], flops_per_launch)},
         "cpu_baseline": cpu,

@@ -55,7 +55,7 @@ fm_status fm_flow_create(fm_flow* out, const fm_problem* problems, int32_t batch
     set_error("batch %d out of range [1, 2^20]", batch);
     return FM_ERR_INVALID;
   }
-  if (dtype < FM_F64 || dtype > FM_F16) {
+  if (dtype < FM_F64 || dtype > FM_BF16X3) {
     set_error("unknown dtype %d", dtype);
     return FM_ERR_INVALID;
   }

@@ -193,7 +193,7 @@ fm_status Flow::ensure_hredu(size_t count) {
 // ------------------------------------------------------------------ configs
 static int pad_order(int n) { return (n + 63) / 64 * 64; }
 
-static int default_bk(int dt) { return dt == DT_F64 ? 16 : (dt == DT_F32 ? 32 : 64); }
+static int default_bk(int dt) { return dt == DT_F64 ? 16 : (dt == DT_F32 ? 32 : 64); }  // BF16X3: 64
 
 static GemmCfg default_cfg(int d, int np) {
   GemmCfg c;
@@ -206,8 +206,8 @@ static GemmCfg default_cfg(int d, int np) {
 
 // ---------------------------------------------------------------- autotuner
 // Tile shape per (device, dtype, padded order), chosen by timing every compiled
-// configuration on a batch of products of that order (AFFINE epilogue, the
-// shape of the propagators' first product).  All configurations sum over k in
+// configuration on a batch of products of that order: an RK4 stage pair (the
+// plain product and the product with the fused stage update).  All configurations sum over k in
 // the same order, so the choice changes speed only, never results.  Choices are
 // kept for the process and, with autotune_cache=<file>, across processes
 // (lines "device dtype np bm bk").
@@ -235,24 +235,37 @@ static void tune_store(const std::string& path, int dev, int d, int np, const Ge
   fclose(f);
 }
 
-static double time_cfg(const GemmCfg& c, int np, int nb, void* A, void* B, void* C, GItem* d_items, int* d_ts,
-                       hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  std::vector<GItem> items(nb);
+// Time one RK4 stage pair on `nb` products: the plain product P = A B
+// (EPI_AFFINE) and the product with the fused stage update (EPI_RK4, FP64
+// state and stage accumulator per product), as the fine propagator runs them.
+static double time_cfg(const GemmCfg& c, int np, int nb, void* A, void* B, void* C, double* X, void* Kacc,
+                       GItem* d_items, int* d_ts, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  const size_t esz = dt_size(c.dt), asz = acc_size(c.dt);
+  const size_t np2 = (size_t)np * np;
+  std::vector<GItem> items(2 * nb);
   std::vector<int> ts(nb + 1, 0);
-  const size_t esz = dt_size(c.dt);
   for (int j = 0; j < nb; ++j) {
     GItem& g = items[j];
     memset(&g, 0, sizeof g);
     g.a = A;
     g.b = B;
-    g.out0 = (char*)C + (size_t)j * np * np * esz;
+    g.out0 = (char*)C + (size_t)j * np2 * esz;
     g.s[0] = 1.0;
     g.flags = F_E_NONE;
     g.np = np;
     g.n = np;
+    GItem& r = items[nb + j];
+    r = g;
+    r.b = g.out0;
+    r.out0 = (char*)C + (size_t)(nb + j) * np2 * esz;  // own next-stage operand buffer
+    r.out1 = (char*)Kacc + (size_t)j * np2 * asz;
+    r.x = X + (size_t)j * np2;
+    r.stage = 1;
+    r.s[0] = -1.0;
+    r.s[2] = 1e-3;
     ts[j + 1] = ts[j] + (np / c.bm) * (np / c.bm);
   }
-  if (hipMemcpyAsync(d_items, items.data(), nb * sizeof(GItem), hipMemcpyHostToDevice, st) != hipSuccess ||
+  if (hipMemcpyAsync(d_items, items.data(), 2 * nb * sizeof(GItem), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(d_ts, ts.data(), (nb + 1) * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
     return 1e30;
   const int total = ts[nb];
@@ -261,6 +274,7 @@ static double time_cfg(const GemmCfg& c, int np, int nb, void* A, void* B, void*
   for (int rep = 0; rep < 3; ++rep) {
     if (hipEventRecord(e0, st) != hipSuccess) return 1e30;
     if (launch_gemm(c, EPI_AFFINE, d_items, d_ts, nb, total, grid, nullptr, st) != hipSuccess) return 1e30;
+    if (launch_gemm(c, EPI_RK4, d_items + nb, d_ts, nb, total, grid, nullptr, st) != hipSuccess) return 1e30;
     if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 1e30;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 1e30;
@@ -289,23 +303,27 @@ GemmCfg Flow::pick_cfg(int d, int np) {
   // a batch of products of this order large enough to fill the GPU
   const size_t np2 = (size_t)np * np;
   int nb = (int)std::max<size_t>(1, std::min<size_t>(16, ((size_t)1 << 27) / (np2 * 2)));
-  const size_t esz = dt_size(d);
-  void *A = nullptr, *B = nullptr, *C = nullptr;
+  const size_t esz = dt_size(d), asz = acc_size(d);
+  void *A = nullptr, *B = nullptr, *C = nullptr, *Kacc = nullptr;
+  double* Xs = nullptr;
   GItem* di = nullptr;
   int* dts = nullptr;
   hipStream_t st = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   GemmCfg best_c = def;
   bool ok = hipMalloc(&A, np2 * esz) == hipSuccess && hipMalloc(&B, np2 * esz) == hipSuccess &&
-            hipMalloc(&C, np2 * esz * nb) == hipSuccess && hipMalloc((void**)&di, nb * sizeof(GItem)) == hipSuccess &&
+            hipMalloc(&C, np2 * esz * 2 * nb) == hipSuccess && hipMalloc(&Kacc, np2 * asz * nb) == hipSuccess &&
+            hipMalloc((void**)&Xs, np2 * 8 * nb) == hipSuccess &&
+            hipMalloc((void**)&di, 2 * nb * sizeof(GItem)) == hipSuccess &&
             hipMalloc((void**)&dts, (nb + 1) * sizeof(int)) == hipSuccess &&
             hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
             hipEventCreate(&e1) == hipSuccess && fill_pattern(A, d, (int64_t)np2, st) == hipSuccess &&
-            fill_pattern(B, d, (int64_t)np2, st) == hipSuccess;
+            fill_pattern(B, d, (int64_t)np2, st) == hipSuccess &&
+            fill_pattern(Xs, DT_F64, (int64_t)np2 * nb, st) == hipSuccess;
   if (ok) {
     double best = 1e30;
     for (const GemmCfg& c : cand) {
-      const double ms = time_cfg(c, np, nb, A, B, C, di, dts, st, e0, e1);
+      const double ms = time_cfg(c, np, nb, A, B, C, Xs, Kacc, di, dts, st, e0, e1);
       if (verbose) fprintf(stderr, "[fm] autotune dt=%d np=%d bm=%d bk=%d: %.3f ms\n", d, np, c.bm, c.bk, ms);
       if (ms < best) {
         best = ms;
@@ -318,6 +336,8 @@ GemmCfg Flow::pick_cfg(int d, int np) {
   if (A) (void)hipFree(A);
   if (B) (void)hipFree(B);
   if (C) (void)hipFree(C);
+  if (Kacc) (void)hipFree(Kacc);
+  if (Xs) (void)hipFree(Xs);
   if (di) (void)hipFree(di);
   if (dts) (void)hipFree(dts);
   if (e0) (void)hipEventDestroy(e0);

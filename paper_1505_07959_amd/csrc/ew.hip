@@ -33,18 +33,26 @@ __device__ __forceinline__ __bf16 cvt<__bf16>(double v) { return (__bf16)(float)
 template <>
 __device__ __forceinline__ _Float16 cvt<_Float16>(double v) { return (_Float16)(float)v; }
 
-template <class T>
+// operand-type store; SPLIT: hi plane at e, lo plane at e + plane
+template <class T, bool SPLIT>
+__device__ __forceinline__ void st_cvt(T* dst, int64_t e, int64_t plane, double v) {
+  const T hi = cvt<T>(v);
+  dst[e] = hi;
+  if constexpr (SPLIT) dst[e + plane] = cvt<T>(v - (double)(float)hi);
+}
+
+template <class T, bool SPLIT = false>
 __global__ void k_convert(T* __restrict__ dst, const double* __restrict__ src, double shift, int n, int np) {
   const int64_t total = (int64_t)np * np;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e / np, j = e % np;
     double v = src[e];
     if (i == j && i < n) v += shift;
-    dst[e] = cvt<T>(v);
+    st_cvt<T, SPLIT>(dst, e, total, v);
   }
 }
 
-template <class T>
+template <class T, bool SPLIT = false>
 __global__ void k_prep(const PrepItem* __restrict__ items, const int* __restrict__ live) {
   const PrepItem it = items[blockIdx.y];
   if (live != nullptr && live[it.inst] == 0) return;
@@ -52,7 +60,7 @@ __global__ void k_prep(const PrepItem* __restrict__ items, const int* __restrict
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < it.count; e += (int64_t)gridDim.x * blockDim.x) {
     const double v = it.u[e];
     if (it.fo) it.fo[e] = v;
-    y[e] = cvt<T>(v);
+    st_cvt<T, SPLIT>(y, e, it.count, v);
   }
 }
 
@@ -311,6 +319,9 @@ hipError_t convert_f64(void* dst, int dt, const double* src, double shift, int n
     case DT_F32: hipLaunchKernelGGL(k_convert<float>, g, b, 0, st, (float*)dst, src, shift, n, np); break;
     case DT_BF16: hipLaunchKernelGGL(k_convert<__bf16>, g, b, 0, st, (__bf16*)dst, src, shift, n, np); break;
     case DT_F16: hipLaunchKernelGGL(k_convert<_Float16>, g, b, 0, st, (_Float16*)dst, src, shift, n, np); break;
+    case DT_BF16X3:
+      hipLaunchKernelGGL((k_convert<__bf16, true>), g, b, 0, st, (__bf16*)dst, src, shift, n, np);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -323,6 +334,7 @@ hipError_t fill_pattern(void* dst, int dt, int64_t count, hipStream_t st) {
     case DT_F32: hipLaunchKernelGGL(k_fill<float>, g, b, 0, st, (float*)dst, count); break;
     case DT_BF16: hipLaunchKernelGGL(k_fill<__bf16>, g, b, 0, st, (__bf16*)dst, count); break;
     case DT_F16: hipLaunchKernelGGL(k_fill<_Float16>, g, b, 0, st, (_Float16*)dst, count); break;
+    case DT_BF16X3: hipLaunchKernelGGL(k_fill<__bf16>, g, b, 0, st, (__bf16*)dst, 2 * count); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -369,6 +381,7 @@ hipError_t launch_prep(const PrepItem* items, int nitems, int dt, const int* liv
     case DT_F32: hipLaunchKernelGGL(k_prep<float>, g, b, 0, st, items, live); break;
     case DT_BF16: hipLaunchKernelGGL(k_prep<__bf16>, g, b, 0, st, items, live); break;
     case DT_F16: hipLaunchKernelGGL(k_prep<_Float16>, g, b, 0, st, items, live); break;
+    case DT_BF16X3: hipLaunchKernelGGL((k_prep<__bf16, true>), g, b, 0, st, items, live); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

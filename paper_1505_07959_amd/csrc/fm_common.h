@@ -9,9 +9,12 @@
 namespace fm {
 
 // Product arithmetic (same numbering as fm_dtype in include/fm.h).
-enum Dt : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3 };
+// DT_BF16X3: split BF16, a matrix is two BF16 planes (hi, lo = bf16(x - hi))
+// stored back to back; products are A_hi B_hi + A_hi B_lo + A_lo B_hi.
+enum Dt : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3, DT_BF16X3 = 4 };
 
-inline int dt_size(int dt) { return dt == DT_F64 ? 8 : (dt == DT_F32 ? 4 : 2); }
+// bytes per matrix element in the operand type (both planes for DT_BF16X3)
+inline int dt_size(int dt) { return dt == DT_F64 ? 8 : (dt == DT_F32 || dt == DT_BF16X3 ? 4 : 2); }
 // accumulator element size (FP64 for the FP64 path, FP32 otherwise)
 inline int acc_size(int dt) { return dt == DT_F64 ? 8 : 4; }
 

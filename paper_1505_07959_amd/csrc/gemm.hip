@@ -67,6 +67,15 @@ template <> struct Tr<DT_F16> {
   using G16 = h8; using LV = h8;
   static constexpr int MI = 32, V = 8, NACC = 16;
 };
+// split BF16: every operand matrix is two BF16 planes (hi, then lo at +np^2)
+template <> struct Tr<DT_BF16X3> {
+  using T = __bf16; using Acc = float; using AccV = f16v;
+  using G16 = bf8; using LV = bf8;
+  static constexpr int MI = 32, V = 8, NACC = 16;
+};
+
+// K segments of a product: 1, or 3 for split BF16 (A_hi B_hi, A_hi B_lo, A_lo B_hi)
+template <int DT> constexpr int nseg() { return DT == DT_BF16X3 ? 3 : 1; }
 
 template <int DT>
 __device__ __forceinline__ void mma(typename Tr<DT>::AccV& acc, const typename Tr<DT>::LV& a,
@@ -77,7 +86,7 @@ __device__ __forceinline__ void mma(typename Tr<DT>::AccV& acc, const typename T
   } else if constexpr (DT == DT_F32) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t], b[t], acc, 0, 0, 0);
-  } else if constexpr (DT == DT_BF16) {
+  } else if constexpr (DT == DT_BF16 || DT == DT_BF16X3) {
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
   } else {
     acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
@@ -110,58 +119,69 @@ __device__ __forceinline__ double from_op<__bf16>(__bf16 v) { return (double)(fl
 template <>
 __device__ __forceinline__ double from_op<_Float16>(_Float16 v) { return (double)(float)v; }
 
+// Operand-type element access; split BF16 stores hi = bf16(v) and
+// lo = bf16(v - hi) in the second plane.
+template <int DT>
+__device__ __forceinline__ double ld_op(const void* p, int64_t idx, int64_t np2) {
+  using T = typename Tr<DT>::T;
+  if constexpr (DT == DT_BF16X3) return from_op(((const T*)p)[idx]) + from_op(((const T*)p)[idx + np2]);
+  else return from_op(((const T*)p)[idx]);
+}
+template <int DT>
+__device__ __forceinline__ void st_op(void* p, int64_t idx, int64_t np2, double v) {
+  using T = typename Tr<DT>::T;
+  const T hi = to_op<T>(v);
+  ((T*)p)[idx] = hi;
+  if constexpr (DT == DT_BF16X3) ((T*)p)[idx + np2] = to_op<T>(v - from_op(hi));
+}
+
 // Fused epilogue for one element (gr, gc) of item `it` (idx = gr*np + gc).
 template <int DT, int EPI>
 __device__ __forceinline__ void epilogue(const GItem& it, int n, int64_t idx, bool diag, double a) {
-  using T = typename Tr<DT>::T;
   using Acc = typename Tr<DT>::Acc;
   const double* s = it.s;
+  const int64_t np2 = (int64_t)it.np * it.np;
   if constexpr (EPI == EPI_AFFINE) {
     double v = s[0] * a;
     if (!(it.flags & F_E_NONE))
-      v += s[1] * ((it.flags & F_E_F64) ? ((const double*)it.in0)[idx] : from_op(((const T*)it.in0)[idx]));
+      v += s[1] * ((it.flags & F_E_F64) ? ((const double*)it.in0)[idx] : ld_op<DT>(it.in0, idx, np2));
     if (diag) v += s[2];
     if (it.flags & F_OUT0_F64) ((double*)it.out0)[idx] = v;
-    else ((T*)it.out0)[idx] = to_op<T>(v);
+    else st_op<DT>(it.out0, idx, np2, v);
   } else if constexpr (EPI == EPI_RK4 || EPI == EPI_EULER) {
     double k = s[0] * a;
     if (!(it.flags & F_E_NONE))
-      k += s[1] * ((it.flags & F_E_F64) ? ((const double*)it.in0)[idx] : from_op(((const T*)it.in0)[idx]));
+      k += s[1] * ((it.flags & F_E_F64) ? ((const double*)it.in0)[idx] : ld_op<DT>(it.in0, idx, np2));
     const double h = s[2];
     const double x = it.x[idx];
     if constexpr (EPI == EPI_EULER) {
       const double xn = x + h * k;
       ((double*)it.out1)[idx] = xn;
-      ((T*)it.out0)[idx] = to_op<T>(xn);
+      st_op<DT>(it.out0, idx, np2, xn);
     } else {
       Acc* K = (Acc*)it.out1;
-      T* Y = (T*)it.out0;
       switch (it.stage) {
-        case 1: K[idx] = (Acc)k; Y[idx] = to_op<T>(x + 0.5 * h * k); break;
-        case 2: K[idx] = (Acc)((double)K[idx] + 2.0 * k); Y[idx] = to_op<T>(x + 0.5 * h * k); break;
-        case 3: K[idx] = (Acc)((double)K[idx] + 2.0 * k); Y[idx] = to_op<T>(x + h * k); break;
+        case 1: K[idx] = (Acc)k; st_op<DT>(it.out0, idx, np2, x + 0.5 * h * k); break;
+        case 2: K[idx] = (Acc)((double)K[idx] + 2.0 * k); st_op<DT>(it.out0, idx, np2, x + 0.5 * h * k); break;
+        case 3: K[idx] = (Acc)((double)K[idx] + 2.0 * k); st_op<DT>(it.out0, idx, np2, x + h * k); break;
         default: {
           const double xn = x + (h / 6.0) * ((double)K[idx] + k);
           it.x[idx] = xn;
-          Y[idx] = to_op<T>(xn);
+          st_op<DT>(it.out0, idx, np2, xn);
         }
       }
     }
   } else if constexpr (EPI == EPI_POLYP) {
-    const T* K = (const T*)it.in0;
-    const T* K2 = (const T*)it.in1;
-    double v = s[1] * from_op(K[idx]) + s[2] * from_op(K2[idx]) + s[3] * a;
+    double v = s[1] * ld_op<DT>(it.in0, idx, np2) + s[2] * ld_op<DT>(it.in1, idx, np2) + s[3] * a;
     if (diag) v += s[0];
-    ((T*)it.out0)[idx] = to_op<T>(v);
-    ((T*)it.out1)[idx] = to_op<T>(a);
+    st_op<DT>(it.out0, idx, np2, v);
+    st_op<DT>(it.out1, idx, np2, a);
   } else {  // EPI_POLYX
-    const T* K = (const T*)it.in0;
-    const T* K2 = (const T*)it.in1;
-    const T* K3 = (const T*)it.in2;
-    double v = a + s[5] * from_op(K[idx]) + s[6] * from_op(K2[idx]) + s[7] * from_op(K3[idx]);
+    double v = a + s[5] * ld_op<DT>(it.in0, idx, np2) + s[6] * ld_op<DT>(it.in1, idx, np2) +
+               s[7] * ld_op<DT>(it.in2, idx, np2);
     if (diag) v += s[4];
     ((double*)it.out1)[idx] = v;
-    ((T*)it.out0)[idx] = to_op<T>(v);
+    st_op<DT>(it.out0, idx, np2, v);
   }
   (void)n;
 }
@@ -257,12 +277,19 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
     G16 rb[B_PER_T][V];
     bool b_active[B_PER_T];
 
-    auto gload = [&](int k0) {
+    const int64_t np2 = (int64_t)np * np;
+    const int nkps = np / BK;  // K tiles per segment
+    auto gload = [&](int kt) {
+      // segment 0: (A_hi, B_hi); 1: (A_hi, B_lo); 2: (A_lo, B_hi)
+      const int seg = kt / nkps;
+      const int k0 = (kt - seg * nkps) * BK;
+      const T* __restrict__ As_g = Ag + (seg == 2 ? np2 : 0);
+      const T* __restrict__ Bs_g = Bg + (seg == 1 ? np2 : 0);
 #pragma unroll
       for (int u = 0; u < A_PER_T; ++u) {
         const int c = tid + 256 * u;
         const int r = c / (BK / W), cc = c % (BK / W);
-        ra[u] = *(const G16*)(Ag + (int64_t)r * np + k0 + cc * W);
+        ra[u] = *(const G16*)(As_g + (int64_t)r * np + k0 + cc * W);
       }
 #pragma unroll
       for (int u = 0; u < B_PER_T; ++u) {
@@ -271,7 +298,7 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
         if (b_active[u]) {
           const int kb = blk / (BN / W), cb = blk % (BN / W);
 #pragma unroll
-          for (int r = 0; r < V; ++r) rb[u][r] = *(const G16*)(Bg + (int64_t)(k0 + kb * V + r) * np + cb * W);
+          for (int r = 0; r < V; ++r) rb[u][r] = *(const G16*)(Bs_g + (int64_t)(k0 + kb * V + r) * np + cb * W);
         }
       }
     };
@@ -298,13 +325,14 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
       }
     };
 
-    const int nk = np / BK;
+    // K tiles of all segments in sequence (one segment unless split BF16)
+    const int nk = nkps * nseg<DT>();
     gload(0);
     lstore(0);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
       const int cur = kt & 1;
-      if (kt + 1 < nk) gload((kt + 1) * BK);
+      if (kt + 1 < nk) gload(kt + 1);
 #pragma unroll
       for (int ch = 0; ch < BK / KC; ++ch) {
         LV a[RM], b[RN];
@@ -389,7 +417,10 @@ int occupancy_cfg() {
   X(DT_F16, 128, 32)   \
   X(DT_F16, 256, 32)   \
   X(DT_F16, 256, 64)   \
-  X(DT_F16, 64, 64)
+  X(DT_F16, 64, 64)    \
+  X(DT_BF16X3, 128, 64) \
+  X(DT_BF16X3, 256, 32) \
+  X(DT_BF16X3, 64, 64)
 
 hipError_t launch_gemm(const GemmCfg& cfg, int epi, const GItem* items, const int* tile_start, int nitems,
                        int total_tiles, int grid, const int* live, hipStream_t st) {

@@ -24,10 +24,10 @@ FM_FLOW_INV_HOMOTOPY = 1
 FM_FLOW_INV_STEADY = 2
 FM_FLOW_SQRT_STEADY = 3
 
-FM_F64, FM_F32, FM_BF16, FM_F16 = 0, 1, 2, 3
+FM_F64, FM_F32, FM_BF16, FM_F16, FM_BF16X3 = 0, 1, 2, 3, 4
 FM_COARSE_EULER, FM_COARSE_LEARNED = 0, 1
 
-DTYPES = {"f64": FM_F64, "f32": FM_F32, "bf16": FM_BF16, "f16": FM_F16}
+DTYPES = {"f64": FM_F64, "f32": FM_F32, "bf16": FM_BF16, "f16": FM_F16, "bf16x3": FM_BF16X3}
 
 
 class FmError(RuntimeError):

@@ -81,3 +81,18 @@ def test_batched_matches_oracle_iterates(dtype):
         say("  %s kind %d n %3d iters %d err %.2e" % (dtype, kind, A.shape[0], s["iters"], e))
         assert s["iters"] == ref["iters"]
         assert e <= bar
+
+
+def test_batched_split_bf16_meets_pre_refinement_bar():
+    """Split BF16 (hi + lo operands, three BF16 products) brings the inverse
+    half under the 1e-2 pre-refinement bar that plain BF16 misses."""
+    cases = [inputs.batched_instance(i, max_n=256) for i in range(8)]
+    st, stats, X = _run(cases, "bf16x3", refine=False)
+    worst = {HOMOTOPY: 0.0, SQRT: 0.0}
+    for (kind, T, A, Q, lam), s, x in zip(cases, stats, X):
+        ref = _oracle(kind, T, Q, lam, s["iters"])
+        e = rel(x, SpectralAlgebra(Q, lam).to_matrix(ref["U"][-1]))
+        worst[kind] = max(worst[kind], e)
+        say("  bf16x3 kind %d n %3d iters %2d pre %.2e" % (kind, A.shape[0], s["iters"], e))
+    say("worst pre-refinement error (bf16x3): inverse %.2e, square root %.2e" % (worst[HOMOTOPY], worst[SQRT]))
+    assert max(worst.values()) <= 1e-2
