@@ -93,6 +93,13 @@ __device__ __forceinline__ void mma(typename Tr<DT>::AccV& acc, const typename T
   }
 }
 
+// One k-step of the FP64 / FP32 MFMA (scalar operands per lane).
+template <int DT, class S>
+__device__ __forceinline__ void mma1(typename Tr<DT>::AccV& acc, S a, S b) {
+  if constexpr (DT == DT_F64) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  else acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+}
+
 // Row/column (within the MI x MI block) of accumulator register v of `lane`.
 template <int DT>
 __device__ __forceinline__ void acc_pos(int lane, int v, int& r, int& c) {
@@ -211,6 +218,13 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
   static_assert(B_BLOCKS <= 256 || B_BLOCKS % 256 == 0, "B tile split");
   constexpr int A_PER_T = A_CHUNKS / 256;
   constexpr int B_PER_T = B_BLOCKS >= 256 ? B_BLOCKS / 256 : 1;
+  // B column swizzle inside aligned groups of G columns (G columns = 128 bytes
+  // of k-vectors): a thread stores W adjacent columns, so without it the lanes
+  // of one store sit W columns apart and hit the same banks; the XOR with the
+  // W-block index spreads them, and the fragment reads (consecutive columns)
+  // stay a permutation of one aligned group.
+  constexpr int GS = 128 / (V * (int)sizeof(T));
+  auto bswz = [](int c) { return c ^ ((c / W) & (GS - 1)); };
 
   __shared__ __attribute__((aligned(16))) T As[2][BM * LDA_S];
   __shared__ __attribute__((aligned(16))) T Bs[2][BK * BN];
@@ -319,7 +333,7 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
             LV col;
 #pragma unroll
             for (int r = 0; r < V; ++r) col[r] = rb[u][r][w];
-            *(LV*)(&Bs[buf][(kb * BN + cb * W + w) * V]) = col;
+            *(LV*)(&Bs[buf][(kb * BN + bswz(cb * W + w)) * V]) = col;
           }
         }
       }
@@ -341,11 +355,22 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
           a[i] = *(const LV*)(&As[cur][(wr * WM + i * MI + lr) * LDA_S + ch * KC + lq * V]);
 #pragma unroll
         for (int j = 0; j < RN; ++j)
-          b[j] = *(const LV*)(&Bs[cur][((ch * NQ + lq) * BN + wc * WN + j * MI + lr) * V]);
+          b[j] = *(const LV*)(&Bs[cur][((ch * NQ + lq) * BN + bswz(wc * WN + j * MI + lr)) * V]);
+        // k-step outermost: consecutive MFMAs update different accumulators,
+        // so none waits on the previous one's result
+        if constexpr (DT == DT_F64 || DT == DT_F32) {
 #pragma unroll
-        for (int i = 0; i < RM; ++i)
+          for (int t = 0; t < 4; ++t)
 #pragma unroll
-          for (int j = 0; j < RN; ++j) mma<DT>(acc[i][j], a[i], b[j]);
+            for (int i = 0; i < RM; ++i)
+#pragma unroll
+              for (int j = 0; j < RN; ++j) mma1<DT>(acc[i][j], a[i][t], b[j][t]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < RM; ++i)
+#pragma unroll
+            for (int j = 0; j < RN; ++j) mma<DT>(acc[i][j], a[i], b[j]);
+        }
       }
       if (kt + 1 < nk) lstore(cur ^ 1);
       __syncthreads();
