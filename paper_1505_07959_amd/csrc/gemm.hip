@@ -34,10 +34,13 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
+#include <utility>
 
 namespace fm {
 namespace {
 
+typedef float f2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef double d2 __attribute__((ext_vector_type(2)));
@@ -50,29 +53,36 @@ template <> struct Tr<DT_F64> {
   using T = double; using Acc = double; using AccV = d4;
   using G16 = d2;   // one 16-byte global chunk
   using LV = d4;    // one lane's k-vector
+  using FV = d2;    // one pipeline step's fragment (2 k-values)
   static constexpr int MI = 16, V = 4, NACC = 4;
 };
 template <> struct Tr<DT_F32> {
   using T = float; using Acc = float; using AccV = f16v;
-  using G16 = f4; using LV = f4;
+  using G16 = f4; using LV = f4; using FV = f2;
   static constexpr int MI = 32, V = 4, NACC = 16;
 };
 template <> struct Tr<DT_BF16> {
   using T = __bf16; using Acc = float; using AccV = f16v;
-  using G16 = bf8; using LV = bf8;
+  using G16 = bf8; using LV = bf8; using FV = bf8;
   static constexpr int MI = 32, V = 8, NACC = 16;
 };
 template <> struct Tr<DT_F16> {
   using T = _Float16; using Acc = float; using AccV = f16v;
-  using G16 = h8; using LV = h8;
+  using G16 = h8; using LV = h8; using FV = h8;
   static constexpr int MI = 32, V = 8, NACC = 16;
 };
 // split BF16: every operand matrix is two BF16 planes (hi, then lo at +np^2)
 template <> struct Tr<DT_BF16X3> {
   using T = __bf16; using Acc = float; using AccV = f16v;
-  using G16 = bf8; using LV = bf8;
+  using G16 = bf8; using LV = bf8; using FV = bf8;
   static constexpr int MI = 32, V = 8, NACC = 16;
 };
+
+// Calls f(std::integral_constant<int, I>()) for I = 0, 1, ... in order.
+template <class F, int... I>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F&& f) {
+  (f(std::integral_constant<int, I>()), ...);
+}
 
 // K segments of a product: 1, or 3 for split BF16 (A_hi B_hi, A_hi B_lo, A_lo B_hi)
 template <int DT> constexpr int nseg() { return DT == DT_BF16X3 ? 3 : 1; }
@@ -126,71 +136,154 @@ __device__ __forceinline__ double from_op<__bf16>(__bf16 v) { return (double)(fl
 template <>
 __device__ __forceinline__ double from_op<_Float16>(_Float16 v) { return (double)(float)v; }
 
-// Operand-type element access; split BF16 stores hi = bf16(v) and
-// lo = bf16(v - hi) in the second plane.
-template <int DT>
-__device__ __forceinline__ double ld_op(const void* p, int64_t idx, int64_t np2) {
-  using T = typename Tr<DT>::T;
-  if constexpr (DT == DT_BF16X3) return from_op(((const T*)p)[idx]) + from_op(((const T*)p)[idx + np2]);
-  else return from_op(((const T*)p)[idx]);
+// Global-memory access through address-space-1 pointers: the item pointers
+// are generic, and flat instructions would also count against the LDS
+// wait counter, coupling the LDS pipeline to outstanding global loads.
+template <class T> using gptr = const __attribute__((address_space(1))) T*;
+template <class T> using gptr_mut = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ T gld(const void* p, int64_t i) { return ((gptr<T>)p)[i]; }
+template <class T>
+__device__ __forceinline__ void gst(void* p, int64_t i, T v) { ((gptr_mut<T>)p)[i] = v; }
+
+// Four consecutive elements per access (EV = 4): the epilogue moves 16-32
+// byte vectors per lane instead of 2-8 byte scalars.  idx is a multiple of
+// 4 (np is a multiple of 64), so every vector access is naturally aligned.
+constexpr int EV = 4;
+struct V4 {
+  double v[EV];
+};
+template <class T>
+using vec4 = T __attribute__((ext_vector_type(EV)));
+
+template <class T>
+__device__ __forceinline__ V4 gld4(const void* p, int64_t idx) {
+  const vec4<T> w = *(gptr<vec4<T>>)((const T*)p + idx);
+  V4 r;
+#pragma unroll
+  for (int e = 0; e < EV; ++e) r.v[e] = from_op<T>(w[e]);
+  return r;
 }
-template <int DT>
-__device__ __forceinline__ void st_op(void* p, int64_t idx, int64_t np2, double v) {
-  using T = typename Tr<DT>::T;
-  const T hi = to_op<T>(v);
-  ((T*)p)[idx] = hi;
-  if constexpr (DT == DT_BF16X3) ((T*)p)[idx + np2] = to_op<T>(v - from_op(hi));
+template <class T>
+__device__ __forceinline__ void gst4(void* p, int64_t idx, const V4& x) {
+  vec4<T> w;
+#pragma unroll
+  for (int e = 0; e < EV; ++e) w[e] = to_op<T>(x.v[e]);
+  *(gptr_mut<vec4<T>>)((T*)p + idx) = w;
 }
 
-// Fused epilogue for one element (gr, gc) of item `it` (idx = gr*np + gc).
+// Operand-type access; split BF16 stores hi = bf16(v) and lo = bf16(v - hi)
+// in the second plane (at + np^2) and reads back hi + lo.
+template <int DT>
+__device__ __forceinline__ V4 ld_op4(const void* p, int64_t idx, int64_t np2) {
+  using T = typename Tr<DT>::T;
+  V4 r = gld4<T>(p, idx);
+  if constexpr (DT == DT_BF16X3) {
+    const V4 lo = gld4<T>(p, idx + np2);
+#pragma unroll
+    for (int e = 0; e < EV; ++e) r.v[e] += lo.v[e];
+  }
+  return r;
+}
+template <int DT>
+__device__ __forceinline__ void st_op4(void* p, int64_t idx, int64_t np2, const V4& x) {
+  using T = typename Tr<DT>::T;
+  gst4<T>(p, idx, x);
+  if constexpr (DT == DT_BF16X3) {
+    V4 lo;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) lo.v[e] = x.v[e] - from_op<T>(to_op<T>(x.v[e]));
+    gst4<T>(p, idx + np2, lo);
+  }
+}
+
+// Fused epilogue for the four elements (gr, gc .. gc+3) of item `it`
+// (idx = gr*np + gc); element `dpos` (or none, -1) lies on the leading
+// n x n diagonal.  Per element the arithmetic is that of the propagator
+// step being fused: a = (A B)[gr, gc] in the accumulation precision.
 template <int DT, int EPI>
-__device__ __forceinline__ void epilogue(const GItem& it, int n, int64_t idx, bool diag, double a) {
+__device__ __forceinline__ void epilogue4(const GItem& it, int64_t idx, int dpos, const V4& a) {
   using Acc = typename Tr<DT>::Acc;
   const double* s = it.s;
   const int64_t np2 = (int64_t)it.np * it.np;
+  // E = the product's second input (same dtype as the operands, or FP64)
+  auto load_e = [&]() -> V4 {
+    return (it.flags & F_E_F64) ? gld4<double>(it.in0, idx) : ld_op4<DT>(it.in0, idx, np2);
+  };
   if constexpr (EPI == EPI_AFFINE) {
-    double v = s[0] * a;
-    if (!(it.flags & F_E_NONE))
-      v += s[1] * ((it.flags & F_E_F64) ? ((const double*)it.in0)[idx] : ld_op<DT>(it.in0, idx, np2));
-    if (diag) v += s[2];
-    if (it.flags & F_OUT0_F64) ((double*)it.out0)[idx] = v;
-    else st_op<DT>(it.out0, idx, np2, v);
+    V4 v;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) v.v[e] = s[0] * a.v[e];
+    if (!(it.flags & F_E_NONE)) {
+      const V4 E = load_e();
+#pragma unroll
+      for (int e = 0; e < EV; ++e) v.v[e] += s[1] * E.v[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EV; ++e)
+      if (e == dpos) v.v[e] += s[2];
+    if (it.flags & F_OUT0_F64) gst4<double>(it.out0, idx, v);
+    else st_op4<DT>(it.out0, idx, np2, v);
   } else if constexpr (EPI == EPI_RK4 || EPI == EPI_EULER) {
-    double k = s[0] * a;
-    if (!(it.flags & F_E_NONE))
-      k += s[1] * ((it.flags & F_E_F64) ? ((const double*)it.in0)[idx] : ld_op<DT>(it.in0, idx, np2));
+    V4 k;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) k.v[e] = s[0] * a.v[e];
+    if (!(it.flags & F_E_NONE)) {
+      const V4 E = load_e();
+#pragma unroll
+      for (int e = 0; e < EV; ++e) k.v[e] += s[1] * E.v[e];
+    }
     const double h = s[2];
-    const double x = it.x[idx];
+    const V4 x = gld4<double>(it.x, idx);
+    V4 o;
     if constexpr (EPI == EPI_EULER) {
-      const double xn = x + h * k;
-      ((double*)it.out1)[idx] = xn;
-      st_op<DT>(it.out0, idx, np2, xn);
+#pragma unroll
+      for (int e = 0; e < EV; ++e) o.v[e] = x.v[e] + h * k.v[e];
+      gst4<double>(it.out1, idx, o);
     } else {
-      Acc* K = (Acc*)it.out1;
-      switch (it.stage) {
-        case 1: K[idx] = (Acc)k; st_op<DT>(it.out0, idx, np2, x + 0.5 * h * k); break;
-        case 2: K[idx] = (Acc)((double)K[idx] + 2.0 * k); st_op<DT>(it.out0, idx, np2, x + 0.5 * h * k); break;
-        case 3: K[idx] = (Acc)((double)K[idx] + 2.0 * k); st_op<DT>(it.out0, idx, np2, x + h * k); break;
-        default: {
-          const double xn = x + (h / 6.0) * ((double)K[idx] + k);
-          it.x[idx] = xn;
-          st_op<DT>(it.out0, idx, np2, xn);
-        }
+      void* K = it.out1;
+      if (it.stage == 1) {
+        gst4<Acc>(K, idx, k);
+#pragma unroll
+        for (int e = 0; e < EV; ++e) o.v[e] = x.v[e] + 0.5 * h * k.v[e];
+      } else if (it.stage == 2 || it.stage == 3) {
+        V4 kk = gld4<Acc>(K, idx);
+#pragma unroll
+        for (int e = 0; e < EV; ++e) kk.v[e] = kk.v[e] + 2.0 * k.v[e];
+        gst4<Acc>(K, idx, kk);
+        const double c = it.stage == 2 ? 0.5 * h : h;
+#pragma unroll
+        for (int e = 0; e < EV; ++e) o.v[e] = x.v[e] + c * k.v[e];
+      } else {
+        const V4 kk = gld4<Acc>(K, idx);
+#pragma unroll
+        for (int e = 0; e < EV; ++e) o.v[e] = x.v[e] + (h / 6.0) * (kk.v[e] + k.v[e]);
+        gst4<double>(it.x, idx, o);
       }
     }
+    st_op4<DT>(it.out0, idx, np2, o);
   } else if constexpr (EPI == EPI_POLYP) {
-    double v = s[1] * ld_op<DT>(it.in0, idx, np2) + s[2] * ld_op<DT>(it.in1, idx, np2) + s[3] * a;
-    if (diag) v += s[0];
-    st_op<DT>(it.out0, idx, np2, v);
-    st_op<DT>(it.out1, idx, np2, a);
+    const V4 p0 = ld_op4<DT>(it.in0, idx, np2), p1 = ld_op4<DT>(it.in1, idx, np2);
+    V4 v;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) v.v[e] = s[1] * p0.v[e] + s[2] * p1.v[e] + s[3] * a.v[e];
+#pragma unroll
+    for (int e = 0; e < EV; ++e)
+      if (e == dpos) v.v[e] += s[0];
+    st_op4<DT>(it.out0, idx, np2, v);
+    st_op4<DT>(it.out1, idx, np2, a);
   } else {  // EPI_POLYX
-    double v = a + s[5] * ld_op<DT>(it.in0, idx, np2) + s[6] * ld_op<DT>(it.in1, idx, np2) +
-               s[7] * ld_op<DT>(it.in2, idx, np2);
-    if (diag) v += s[4];
-    ((double*)it.out1)[idx] = v;
-    st_op<DT>(it.out0, idx, np2, v);
+    const V4 p0 = ld_op4<DT>(it.in0, idx, np2), p1 = ld_op4<DT>(it.in1, idx, np2),
+             p2 = ld_op4<DT>(it.in2, idx, np2);
+    V4 v;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) v.v[e] = a.v[e] + s[5] * p0.v[e] + s[6] * p1.v[e] + s[7] * p2.v[e];
+#pragma unroll
+    for (int e = 0; e < EV; ++e)
+      if (e == dpos) v.v[e] += s[4];
+    gst4<double>(it.out1, idx, v);
+    st_op4<DT>(it.out0, idx, np2, v);
   }
-  (void)n;
 }
 
 template <int DT, int BM, int BK, int EPI>
@@ -202,6 +295,7 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
   using G16 = typename TR::G16;
   using LV = typename TR::LV;
   using AccV = typename TR::AccV;
+  using FV = typename TR::FV;
   constexpr int MI = TR::MI, V = TR::V, NACC = TR::NACC;
   constexpr int BN = BM;
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -218,6 +312,16 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
   static_assert(B_BLOCKS <= 256 || B_BLOCKS % 256 == 0, "B tile split");
   constexpr int A_PER_T = A_CHUNKS / 256;
   constexpr int B_PER_T = B_BLOCKS >= 256 ? B_BLOCKS / 256 : 1;
+  // pipeline step: SUBV k-values per lane (FP64/FP32: half of the lane's
+  // 4-vector, 2 MFMAs deep; 16-bit: one MFMA), SUB steps per KC chunk
+  constexpr int SUBV = (DT == DT_F64 || DT == DT_F32) ? 2 : V;
+  constexpr int SUB = V / SUBV;
+  constexpr int NSTEP = (BK / KC) * SUB;
+  // global prefetch depth in K tiles: the 16-bit K tiles of the 128-wide
+  // tiles are short next to the memory latency, so their loads are issued
+  // two tiles ahead (the 256-wide tiles have no registers for a second set)
+  constexpr int PF = (DT == DT_F64 || DT == DT_F32 || BM > 128) ? 1 : 2;
+  static_assert(NSTEP % 2 == 0, "pipeline steps per K tile must be even");
   // B column swizzle inside aligned groups of G columns (G columns = 128 bytes
   // of k-vectors): a thread stores W adjacent columns, so without it the lanes
   // of one store sit W columns apart and hit the same banks; the XOR with the
@@ -226,8 +330,13 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
   constexpr int GS = 128 / (V * (int)sizeof(T));
   auto bswz = [](int c) { return c ^ ((c / W) & (GS - 1)); };
 
-  __shared__ __attribute__((aligned(16))) T As[2][BM * LDA_S];
-  __shared__ __attribute__((aligned(16))) T Bs[2][BK * BN];
+  // one LDS block: two stages of A and B tiles during the K loop, reused
+  // by the epilogue to stage accumulators
+  constexpr int A_STAGE = BM * LDA_S, B_STAGE = BK * BN;
+  constexpr int SMEM = 2 * (A_STAGE + B_STAGE) * (int)sizeof(T);
+  __shared__ __attribute__((aligned(16))) char smem[SMEM];
+  T (*As)[A_STAGE] = reinterpret_cast<T (*)[A_STAGE]>(smem);
+  T (*Bs)[B_STAGE] = reinterpret_cast<T (*)[B_STAGE]>(smem + 2 * A_STAGE * sizeof(T));
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -287,23 +396,33 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
 #pragma unroll
         for (int v = 0; v < NACC; ++v) acc[i][j][v] = 0;
 
-    G16 ra[A_PER_T];
-    G16 rb[B_PER_T][V];
+    // PF register staging sets: tile kt's global loads land in set kt % PF
+    G16 ra[PF][A_PER_T];
+    G16 rb[PF][B_PER_T][V];
     bool b_active[B_PER_T];
 
     const int64_t np2 = (int64_t)np * np;
     const int nkps = np / BK;  // K tiles per segment
-    auto gload = [&](int kt) {
+    // Global loads through buffer resources rebased at every K tile: the
+    // per-lane byte offsets are loop-invariant and small, and a resource's
+    // record count is the exact extent of the tile's panel, so a load can
+    // never leave it (out-of-range buffer loads return zero).
+    auto gload = [&](int kt, int set) {
       // segment 0: (A_hi, B_hi); 1: (A_hi, B_lo); 2: (A_lo, B_hi)
       const int seg = kt / nkps;
       const int k0 = (kt - seg * nkps) * BK;
-      const T* __restrict__ As_g = Ag + (seg == 2 ? np2 : 0);
-      const T* __restrict__ Bs_g = Bg + (seg == 1 ? np2 : 0);
+      const T* As_g = Ag + (seg == 2 ? np2 : 0) + k0;
+      const T* Bs_g = Bg + (seg == 1 ? np2 : 0) + (int64_t)k0 * np;
+      const __amdgpu_buffer_rsrc_t ra_rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<T*>(As_g), (short)0, ((BM - 1) * np + BK) * (int)sizeof(T), 0x00020000);
+      const __amdgpu_buffer_rsrc_t rb_rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<T*>(Bs_g), (short)0, ((BK - 1) * np + BN) * (int)sizeof(T), 0x00020000);
 #pragma unroll
       for (int u = 0; u < A_PER_T; ++u) {
         const int c = tid + 256 * u;
         const int r = c / (BK / W), cc = c % (BK / W);
-        ra[u] = *(const G16*)(As_g + (int64_t)r * np + k0 + cc * W);
+        ra[set][u] = __builtin_bit_cast(G16, __builtin_amdgcn_raw_buffer_load_b128(
+                                            ra_rs, (r * np + cc * W) * (int)sizeof(T), 0, 0));
       }
 #pragma unroll
       for (int u = 0; u < B_PER_T; ++u) {
@@ -312,16 +431,18 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
         if (b_active[u]) {
           const int kb = blk / (BN / W), cb = blk % (BN / W);
 #pragma unroll
-          for (int r = 0; r < V; ++r) rb[u][r] = *(const G16*)(Bs_g + (int64_t)(k0 + kb * V + r) * np + cb * W);
+          for (int r = 0; r < V; ++r)
+            rb[set][u][r] = __builtin_bit_cast(G16, __builtin_amdgcn_raw_buffer_load_b128(
+                                                   rb_rs, ((kb * V + r) * np + cb * W) * (int)sizeof(T), 0, 0));
         }
       }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, int set) {
 #pragma unroll
       for (int u = 0; u < A_PER_T; ++u) {
         const int c = tid + 256 * u;
         const int r = c / (BK / W), cc = c % (BK / W);
-        *(G16*)(&As[buf][r * LDA_S + cc * W]) = ra[u];
+        *(G16*)(&As[buf][r * LDA_S + cc * W]) = ra[set][u];
       }
 #pragma unroll
       for (int u = 0; u < B_PER_T; ++u) {
@@ -332,69 +453,133 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
           for (int w = 0; w < W; ++w) {
             LV col;
 #pragma unroll
-            for (int r = 0; r < V; ++r) col[r] = rb[u][r][w];
+            for (int r = 0; r < V; ++r) col[r] = rb[set][u][r][w];
             *(LV*)(&Bs[buf][(kb * BN + bswz(cb * W + w)) * V]) = col;
           }
         }
       }
     };
 
-    // K tiles of all segments in sequence (one segment unless split BF16)
+    // K tiles of all segments in sequence (one segment unless split BF16).
+    // Software pipeline at the granularity of one "step" (SUBV k-values per
+    // lane group of a KC chunk): the fragments of step s+1 are read from LDS
+    // while the MFMAs of step s run.  At the last step of a K tile the next
+    // tile (already in registers) is stored to the other LDS buffer, one
+    // barrier publishes it, its first fragments are requested and only then
+    // are the last MFMAs of the current tile issued, so they cover the LDS
+    // latency; the global loads of tile kt+2 go out right after the barrier.
     const int nk = nkps * nseg<DT>();
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-      const int cur = kt & 1;
-      if (kt + 1 < nk) gload(kt + 1);
+    FV fa0[RM], fb0[RN], fa1[RM], fb1[RN];
+    auto read_frag = [&](FV (&fa)[RM], FV (&fb)[RN], int buf, int sidx) {
+      const int ch = sidx / SUB, sub = sidx % SUB;
 #pragma unroll
-      for (int ch = 0; ch < BK / KC; ++ch) {
-        LV a[RM], b[RN];
+      for (int i = 0; i < RM; ++i)
+        fa[i] = *(const FV*)(&As[buf][(wr * WM + i * MI + lr) * LDA_S + ch * KC + lq * V + sub * SUBV]);
 #pragma unroll
-        for (int i = 0; i < RM; ++i)
-          a[i] = *(const LV*)(&As[cur][(wr * WM + i * MI + lr) * LDA_S + ch * KC + lq * V]);
+      for (int j = 0; j < RN; ++j)
+        fb[j] = *(const FV*)(&Bs[buf][((ch * NQ + lq) * BN + bswz(wc * WN + j * MI + lr)) * V + sub * SUBV]);
+    };
+    auto mfma_step = [&](const FV (&fa)[RM], const FV (&fb)[RN]) {
+      if constexpr (DT == DT_F64 || DT == DT_F32) {
+        // k-value outermost: consecutive MFMAs update different accumulators
 #pragma unroll
-        for (int j = 0; j < RN; ++j)
-          b[j] = *(const LV*)(&Bs[cur][((ch * NQ + lq) * BN + bswz(wc * WN + j * MI + lr)) * V]);
-        // k-step outermost: consecutive MFMAs update different accumulators,
-        // so none waits on the previous one's result
-        if constexpr (DT == DT_F64 || DT == DT_F32) {
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int i = 0; i < RM; ++i)
-#pragma unroll
-              for (int j = 0; j < RN; ++j) mma1<DT>(acc[i][j], a[i][t], b[j][t]);
-        } else {
+        for (int t = 0; t < SUBV; ++t)
 #pragma unroll
           for (int i = 0; i < RM; ++i)
 #pragma unroll
-            for (int j = 0; j < RN; ++j) mma<DT>(acc[i][j], a[i], b[j]);
-        }
+            for (int j = 0; j < RN; ++j) mma1<DT>(acc[i][j], fa[i][t], fb[j][t]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+#pragma unroll
+          for (int j = 0; j < RN; ++j) mma<DT>(acc[i][j], fa[i], fb[j]);
       }
-      if (kt + 1 < nk) lstore(cur ^ 1);
-      __syncthreads();
+    };
+    // One K tile.  Step s (compile-time) computes with fragment set s & 1
+    // and fills the other set.  At the last step the successor tile kt+1
+    // goes from its staging set to the other LDS buffer, one barrier
+    // publishes it, its first fragments are requested, the same staging set
+    // is refilled with tile kt+1+PF (global loads stay in flight for PF K
+    // tiles of MFMA work) and only then are the tile's last MFMAs issued,
+    // covering the LDS latency.  Every K tile runs the same code: after the
+    // last one the boundary work repeats tile nk-1 (clamped indices, never
+    // used), which keeps the loop free of branches that would make the
+    // compiler's LDS wait counts conservative.
+    auto ktile = [&](auto par_c, int kt) {
+      constexpr int set = PF == 2 ? (decltype(par_c)::value ^ 1) : 0;
+      const int cur = kt & 1;
+      static_for(std::make_integer_sequence<int, NSTEP>(), [&](auto s_c) {
+        constexpr int sidx = decltype(s_c)::value;
+        FV(&fa_c)[RM] = (sidx & 1) ? fa1 : fa0;
+        FV(&fb_c)[RN] = (sidx & 1) ? fb1 : fb0;
+        FV(&fa_n)[RM] = (sidx & 1) ? fa0 : fa1;
+        FV(&fb_n)[RN] = (sidx & 1) ? fb0 : fb1;
+        if constexpr (sidx + 1 < NSTEP) {
+          read_frag(fa_n, fb_n, cur, sidx + 1);
+        } else {
+          lstore(cur ^ 1, set);
+          __syncthreads();
+          read_frag(fa_n, fb_n, cur ^ 1, 0);
+          gload(min(kt + 1 + PF, nk - 1), set);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_step(fa_c, fb_c);
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    };
+
+    __syncthreads();  // the previous output tile's epilogue may still read LDS
+    gload(0, 0);
+    lstore(0, 0);
+    gload(min(1, nk - 1), PF - 1);
+    if (PF == 2) gload(min(2, nk - 1), 0);
+    __syncthreads();
+    read_frag(fa0, fb0, 0, 0);
+    if constexpr (PF == 1) {
+      for (int kt = 0; kt < nk; ++kt) ktile(std::integral_constant<int, 0>(), kt);
+    } else {
+      for (int kt = 0; kt < nk; kt += 2) {
+        ktile(std::integral_constant<int, 0>(), kt);
+        if (kt + 1 < nk) ktile(std::integral_constant<int, 1>(), kt + 1);  // nk is odd only for 64-wide tiles
+      }
     }
 
-    // fused epilogue
-    const int n_valid = it.n;
+    // Fused epilogue, staged through LDS in RM passes: in pass i every wave
+    // writes its accumulator row block i (MI rows), then all 256 threads
+    // walk the 2*MI x BN staged rows in row-major order, so the epilogue's
+    // global traffic is coalesced and the accumulators are only ever
+    // indexed statically.
+    {
+      using Acc = typename TR::Acc;
+      constexpr int CROWS = 2 * MI;
+      constexpr int CLD = BN + 16 / (int)sizeof(Acc);
+      static_assert(CROWS * CLD * (int)sizeof(Acc) <= SMEM, "epilogue staging must fit in LDS");
+      Acc* Cs = reinterpret_cast<Acc*>(smem);
+      const int n_valid = it.n;
 #pragma unroll
-    for (int i = 0; i < RM; ++i)
+      for (int i = 0; i < RM; ++i) {
+        __syncthreads();  // K loop / previous pass readers are done with LDS
 #pragma unroll
-      for (int j = 0; j < RN; ++j) {
-        // one MFMA block at a time: keeps the epilogue's loads from being
-        // hoisted all together (register pressure of the 256-wide tiles)
-        __builtin_amdgcn_sched_barrier(0);
+        for (int j = 0; j < RN; ++j)
 #pragma unroll
-        for (int v = 0; v < NACC; ++v) {
-          int r, c;
-          acc_pos<DT>(lane, v, r, c);
-          const int gr = row0 + wr * WM + i * MI + r;
-          const int gc = col0 + wc * WN + j * MI + c;
-          const int64_t idx = (int64_t)gr * np + gc;
-          epilogue<DT, EPI>(it, n_valid, idx, gr == gc && gr < n_valid, (double)acc[i][j][v]);
+          for (int v = 0; v < NACC; ++v) {
+            int r, c;
+            acc_pos<DT>(lane, v, r, c);
+            Cs[(wr * MI + r) * CLD + wc * WN + j * MI + c] = (Acc)acc[i][j][v];
+          }
+        __syncthreads();
+        for (int e = tid; e < CROWS * BN / EV; e += 256) {
+          const int rr = (e * EV) / BN, cc = (e * EV) % BN;
+          const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
+          const int gc = col0 + cc;
+          V4 a;
+#pragma unroll
+          for (int q = 0; q < EV; ++q) a.v[q] = (double)Cs[rr * CLD + cc + q];
+          const int dpos = (gr >= gc && gr < gc + EV && gr < n_valid) ? gr - gc : -1;
+          epilogue4<DT, EPI>(it, (int64_t)gr * np + gc, dpos, a);
         }
       }
+    }
   }
 }
 
