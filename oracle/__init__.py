@@ -30,5 +30,6 @@ above is Q diag(x) Q^T where x runs the *same* discrete algorithm on lam.
 Parity status per function is recorded in each module header.
 """
 
-from .core import MatrixAlgebra, SpectralAlgebra, HOMOTOPY, STEADY_INV, SQRT, KINDS  # noqa: F401
+from .core import MatrixAlgebra, SpectralAlgebra, HOMOTOPY, STEADY_INV, SQRT, EXP, INV_LINEAR  # noqa: F401
+from .core import KINDS, LINEAR_KINDS, INVERSE_KINDS  # noqa: F401
 from . import flows, integrators, parareal, exact, refine, learned, mlp  # noqa: F401

@@ -19,7 +19,11 @@ import numpy as np
 HOMOTOPY = 1    # dX/dt = X (I - A) X, X(0) = I, X(1) = A^{-1} (Sec. 2, Example 1)
 STEADY_INV = 2  # dX/dt = X - X A X, stable steady state A^{-1}
 SQRT = 3        # dX/dt = A - X^2, stable steady state A^{1/2} (A SPD)
-KINDS = (HOMOTOPY, STEADY_INV, SQRT)
+EXP = 4         # dQ/dt = A Q, Q(0) = I, Q(1) = exp(A) (Sec. 2, Example 2)
+INV_LINEAR = 5  # dX/dt = I - A X, stable steady state A^{-1} (Sec. 4, Example 5)
+KINDS = (HOMOTOPY, STEADY_INV, SQRT, EXP, INV_LINEAR)
+LINEAR_KINDS = (EXP, INV_LINEAR)
+INVERSE_KINDS = (HOMOTOPY, STEADY_INV, INV_LINEAR)
 
 
 class MatrixAlgebra:

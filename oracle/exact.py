@@ -5,6 +5,9 @@ Targets:
   (Sec. 2, Example 1) and the stable root of dX/dt = X - X A X.
 * A^{1/2} = Q diag(sqrt(lam)) Q^T from a symmetric eigendecomposition: the
   stable root of dX/dt = A - X^2 for SPD A.
+* exp(T A) by scipy.linalg.expm (scaling and squaring with Pade): the value
+  Q(T) of the exponential flow of Sec. 2, Example 2; A^{-1} again for the
+  linear flow dX/dt = I - A X of Sec. 4, Example 5.
 
 Closed-form solutions of the three flows for an arbitrary invertible start X0
 (X0 need not commute with A; derived here, not printed in the paper):
@@ -16,6 +19,8 @@ Closed-form solutions of the three flows for an arbitrary invertible start X0
   with W'' = A W, W(0) = I, W'(0) = X0, i.e.
   W(t) = cosh(sqrt(A) t) + sqrt(A)^{-1} sinh(sqrt(A) t) X0,
   W'(t) = sqrt(A) sinh(sqrt(A) t) + cosh(sqrt(A) t) X0.
+* exponential dQ/dt = A Q:  Q(t) = exp(t A) X0.
+* linear inverse dX/dt = I - A X:  X(t) = A^{-1} + exp(-t A) (X0 - A^{-1}).
 
 Parity: the targets are pinned by their defining identities (A X = I,
 X^2 = A with X SPD); the closed forms by finite-difference derivatives matching
@@ -24,7 +29,7 @@ the flow field (tests/test_oracle_flows.py).
 
 import numpy as np
 
-from .core import HOMOTOPY, STEADY_INV, SQRT
+from .core import HOMOTOPY, STEADY_INV, SQRT, EXP, INV_LINEAR
 
 
 def inverse_lu(A):
@@ -38,6 +43,11 @@ def sqrt_eig(A):
     if lam.min() <= 0:
         raise ValueError("matrix square root needs an SPD matrix")
     return (Q * np.sqrt(lam)) @ Q.T
+
+
+def expm(A):
+    import scipy.linalg
+    return scipy.linalg.expm(np.asarray(A, dtype=np.float64))
 
 
 def _fun_sym(A, f):
@@ -62,6 +72,11 @@ def closed_form(kind, A, X0, t):
         W = C + S_over @ X0
         Wd = S_times + C @ X0
         return Wd @ np.linalg.inv(W)
+    if kind == EXP:
+        return expm(t * A) @ X0
+    if kind == INV_LINEAR:
+        Ai = inverse_lu(A)
+        return Ai + expm(-t * A) @ (X0 - Ai)
     raise ValueError(kind)
 
 
@@ -76,13 +91,20 @@ def closed_form_scalar(kind, lam, t):
         s = np.sqrt(lam)
         th = np.tanh(s * t)
         return s * (1.0 + s * th) / (s + th)
+    if kind == EXP:
+        return np.exp(lam * t)
+    if kind == INV_LINEAR:
+        return 1.0 / lam + np.exp(-lam * t) * (1.0 - 1.0 / lam)
     raise ValueError(kind)
 
 
-def target(kind, A):
-    """f(A) reached by the flow: A^{-1} (HOMOTOPY at T = 1, STEADY_INV) or A^{1/2}."""
-    if kind in (HOMOTOPY, STEADY_INV):
+def target(kind, A, T=1.0):
+    """f(A) reached by the flow: A^{-1} (HOMOTOPY at T = 1, STEADY_INV,
+    INV_LINEAR), A^{1/2}, or exp(T A) (EXP at time T)."""
+    if kind in (HOMOTOPY, STEADY_INV, INV_LINEAR):
         return inverse_lu(A)
+    if kind == EXP:
+        return expm(T * A)
     if kind == SQRT:
         return sqrt_eig(A)
     raise ValueError(kind)

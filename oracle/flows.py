@@ -9,17 +9,21 @@
   the root having eigenvalues of negative real part; here D F = -Id at A^{-1}).
 * SQRT: dX/dt = A - X^2 for SPD A; stable root the principal square root
   (differential eigenvalues -(sqrt(lam_i) + sqrt(lam_j))).
+* EXP: dQ/dt = A Q with Q(0) = I (Sec. 2, Example 2: A(t) = t A, Q(t) =
+  exp(t A), Q(1) = exp(A)).
+* INV_LINEAR: dX/dt = I - A X (Sec. 4, Example 5), linear, stable steady
+  state A^{-1} when the eigenvalues of A have positive real part.
 
 Association order of the products is part of the definition of the discrete
 method: X (M X) for the homotopy with M = A - I, X (A X) for STEADY_INV, X X for
-SQRT.
+SQRT; the linear flows multiply A from the left.
 
 Parity: pinned by the closed-form solutions in ``exact`` (including starting
 values that do not commute with A) and by the fourth-order convergence of RK4
 towards them (tests/test_oracle_flows.py).
 """
 
-from .core import HOMOTOPY, STEADY_INV, SQRT
+from .core import HOMOTOPY, STEADY_INV, SQRT, EXP, INV_LINEAR
 
 
 def shifted(alg, A):
@@ -37,4 +41,8 @@ def rhs(alg, kind, X, A, M=None):
         return X - alg.mul(X, alg.mul(A, X))
     if kind == SQRT:
         return A - alg.mul(X, X)
+    if kind == EXP:
+        return alg.mul(A, X)
+    if kind == INV_LINEAR:
+        return alg.eye() - alg.mul(A, X)
     raise ValueError("unknown flow kind %r" % (kind,))

@@ -22,12 +22,12 @@ reduction in the commuting case and by quadratic convergence to the targets of
 
 import numpy as np
 
-from .core import HOMOTOPY, STEADY_INV, SQRT
+from .core import HOMOTOPY, STEADY_INV, SQRT, INV_LINEAR
 
 
 def residual(alg, kind, A, X):
     """(R, relative residual) for the target of `kind`."""
-    if kind in (HOMOTOPY, STEADY_INV):
+    if kind in (HOMOTOPY, STEADY_INV, INV_LINEAR):
         I = alg.eye()
         R = I - alg.mul(A, X)
         return R, alg.fro(R) / alg.fro(I)
@@ -46,7 +46,7 @@ def solve_sylvester_sym(alg, X, R):
 
 
 def refine_step(alg, kind, A, X, R):
-    if kind in (HOMOTOPY, STEADY_INV):
+    if kind in (HOMOTOPY, STEADY_INV, INV_LINEAR):
         return X + alg.mul(X, R)
     if kind == SQRT:
         return X + solve_sylvester_sym(alg, X, R)

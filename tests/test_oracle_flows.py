@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from oracle import MatrixAlgebra, SpectralAlgebra, HOMOTOPY, STEADY_INV, SQRT, KINDS
+from oracle import MatrixAlgebra, SpectralAlgebra, HOMOTOPY, STEADY_INV, SQRT, EXP, INV_LINEAR, KINDS
 from oracle import flows, integrators, exact
 from paper_1505_07959_amd import inputs
 
@@ -163,3 +163,61 @@ def test_steady_flows_reach_target(kind, T):
     A, Q, lam = inputs.spd(6, "uniform", 0.5, 2.0, 3)
     X = exact.closed_form(kind, A, np.eye(6), T)
     assert exact.rel_fro(X, exact.target(kind, A)) < 1e-6
+
+
+# ---- the linear flows (Sec. 2 Example 2; Sec. 4 Example 5)
+
+def _taylor4(Z):
+    """I + Z + Z^2/2 + Z^3/6 + Z^4/24."""
+    n = Z.shape[0]
+    out, term = np.eye(n), np.eye(n)
+    for j in range(1, 5):
+        term = term @ Z / j
+        out = out + term
+    return out
+
+
+def test_rk4_on_linear_fields_is_the_taylor_polynomial():
+    """Classical RK4 applied to X' = L(X) with L linear reproduces the
+    degree-4 Taylor polynomial of the exact step: X+ = P4(hA) X for X' = A X,
+    and X+ = A^{-1} + P4(-hA)(X - A^{-1}) for the affine X' = I - A X.  A
+    non-symmetric A and a start not commuting with it."""
+    n, h = 5, 0.3
+    A = inputs.nonsymmetric(n, 7, shift=1.5, spread=0.4)
+    X = inputs.perturbed_identity(n, 8, eps=0.3) + 0.2 * inputs.nonsymmetric(n, 9, shift=0.0, spread=1.0)
+    alg = MatrixAlgebra(n)
+    got = integrators.rk4_step(alg, EXP, X, A, h)
+    assert np.linalg.norm(got - _taylor4(h * A) @ X) <= 1e-14 * np.linalg.norm(got)
+    Ai = np.linalg.inv(A)
+    got = integrators.rk4_step(alg, INV_LINEAR, X, A, h)
+    want = Ai + _taylor4(-h * A) @ (X - Ai)
+    assert np.linalg.norm(got - want) <= 1e-13 * np.linalg.norm(want)
+    # forward Euler is the degree-1 polynomial
+    got = integrators.euler_step(alg, EXP, X, A, h)
+    assert np.linalg.norm(got - (X + h * A @ X)) <= 1e-15 * np.linalg.norm(got)
+
+
+def test_expm_pins():
+    """exp by the library routine against independent facts: the eigenvalue
+    form for symmetric A, exp(A) exp(-A) = I, and the rotation generator."""
+    A, Q, lam = inputs.spd(6, "uniform", -1.0, 2.0, 3)
+    E = exact.expm(A)
+    assert np.linalg.norm(E - (Q * np.exp(lam)) @ Q.T) <= 1e-13 * np.linalg.norm(E)
+    B = inputs.nonsymmetric(6, 4, shift=0.0, spread=1.0)
+    assert np.linalg.norm(exact.expm(B) @ exact.expm(-B) - np.eye(6)) < 1e-12
+    th = 0.7
+    R = exact.expm(np.array([[0.0, -th], [th, 0.0]]))
+    assert np.allclose(R, [[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]], atol=1e-15)
+
+
+def test_linear_inverse_flow_reaches_the_inverse():
+    """X' = I - A X from X0 = 0 tends to A^{-1} (Example 5); the closed form at
+    large t and many Euler steps both get there."""
+    A, Q, lam = inputs.spd(6, "uniform", 0.5, 2.0, 12)
+    Ai = np.linalg.inv(A)
+    X = exact.closed_form(INV_LINEAR, A, np.zeros((6, 6)), 60.0)
+    assert np.linalg.norm(X - Ai) <= 1e-12 * np.linalg.norm(Ai)
+    Xe = integrators.coarse(MatrixAlgebra(6), INV_LINEAR, A, np.zeros((6, 6)), 60.0, 0.0, 600)
+    assert np.linalg.norm(Xe - Ai) <= 1e-10 * np.linalg.norm(Ai)
+    assert exact.target(INV_LINEAR, A) is not None
+    assert np.allclose(exact.target(EXP, A, 0.5), (Q * np.exp(0.5 * lam)) @ Q.T, atol=1e-13)
