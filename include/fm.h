@@ -53,7 +53,15 @@ typedef enum {
   FM_FLOW_INV_STEADY = 2,
   /* dX/dt = A - X^2, A symmetric positive definite: stable steady state the
    * principal square root A^{1/2}.                                           */
-  FM_FLOW_SQRT_STEADY = 3
+  FM_FLOW_SQRT_STEADY = 3,
+  /* Sec. 2, Example 2: with A(t) = t A, Q(t) = exp(t A) solves dQ/dt = A Q,
+   * Q(0) = I; Q(T) = exp(T A).  One product per RK4 stage; no refinement
+   * (max_refine must be 0).                                                 */
+  FM_FLOW_EXP = 4,
+  /* Sec. 4, Example 5: dX/dt = I - A X, linear, stable steady state A^{-1}
+   * when the eigenvalues of A have positive real part.  One product per RK4
+   * stage; Newton-Schulz refinement as for the other inverse flows.       */
+  FM_FLOW_INV_LINEAR = 5
 } fm_flow_kind;
 
 /* Arithmetic of the dense products of the propagators (MFMA input type).  The
@@ -72,6 +80,13 @@ typedef enum {
                              per-slice fallback to Euler (see fm_params)    */
 } fm_coarse;
 
+/* Fine propagator F. */
+typedef enum {
+  FM_FINE_RK4 = 0,    /* classical four-stage Runge-Kutta steps */
+  FM_FINE_EULER = 1   /* forward Euler steps (the fine scheme of the paper's
+                         Example 1, Sec. 2) */
+} fm_fine;
+
 typedef struct {
   int32_t kind;      /* fm_flow_kind */
   int32_t reserved;  /* must be 0 */
@@ -83,7 +98,7 @@ typedef struct {
 
 /* Problem statement of Alg. 1 (Sec. 2): time interval [0, T] in N uniform
  * slices T_n = n T / N; G = coarse_steps coarse steps per slice; F =
- * fine_steps classical RK4 steps per slice.  Iteration k computes U^{k+1}
+ * fine_steps steps of the fine scheme (fine_method) per slice.  Iteration k computes U^{k+1}
  * from U^k; it stops after the first k with
  *     max_n ||U^{k+1}_n - U^k_n||_F / ||U^{k+1}_n||_F <= tol,
  * or after max_iter iterations, or at k + 1 = N (then U equals the serial fine
@@ -101,6 +116,8 @@ typedef struct {
   int32_t max_refine;    /* >= 0 */
   double tol;            /* >= 0 */
   double refine_tol;     /* >= 0 */
+  int32_t fine_method;   /* fm_fine */
+  int32_t reserved;      /* must be 0 */
 } fm_params;
 
 typedef struct {

@@ -61,7 +61,7 @@ fm_status fm_flow_create(fm_flow* out, const fm_problem* problems, int32_t batch
   }
   for (int i = 0; i < batch; ++i) {
     const fm_problem& p = problems[i];
-    if (p.kind < FM_FLOW_INV_HOMOTOPY || p.kind > FM_FLOW_SQRT_STEADY) {
+    if (p.kind < FM_FLOW_INV_HOMOTOPY || p.kind > FM_FLOW_INV_LINEAR) {
       set_error("problem %d: unknown flow kind %d", i, p.kind);
       return FM_ERR_INVALID;
     }
@@ -98,16 +98,23 @@ fm_status fm_parareal_solve(fm_flow f, const double* const* X0, double* const* X
     const fm_params& p = prm[i];
     if (!(p.T > 0) || !std::isfinite(p.T) || p.N < 1 || p.N > 4096 || p.coarse_steps < 1 || p.fine_steps < 1 ||
         p.max_iter < 0 || p.max_refine < 0 || !(p.tol >= 0) || !(p.refine_tol >= 0) ||
-        (p.coarse != FM_COARSE_EULER && p.coarse != FM_COARSE_LEARNED)) {
-      set_error("prm[%d]: need T > 0, 1 <= N <= 4096, steps >= 1, max_iter >= 0, tol >= 0, known coarse", i);
+        (p.coarse != FM_COARSE_EULER && p.coarse != FM_COARSE_LEARNED) ||
+        (p.fine_method != FM_FINE_RK4 && p.fine_method != FM_FINE_EULER) || p.reserved != 0) {
+      set_error("prm[%d]: need T > 0, 1 <= N <= 4096, steps >= 1, max_iter >= 0, tol >= 0, known coarse and "
+                "fine schemes, reserved == 0", i);
+      return FM_ERR_INVALID;
+    }
+    if (f->impl.inst[i].kind == FM_FLOW_EXP && p.max_refine != 0) {
+      set_error("prm[%d]: the exponential flow has no refinement (max_refine must be 0)", i);
       return FM_ERR_INVALID;
     }
     if (f->impl.inst[i].kind == FM_FLOW_INV_HOMOTOPY && p.T != 1.0) {
       set_error("prm[%d]: the homotopy flow reaches A^{-1} at T = 1 only", i);
       return FM_ERR_INVALID;
     }
-    if (p.coarse == FM_COARSE_LEARNED && f->impl.inst[i].kind == FM_FLOW_SQRT_STEADY) {
-      set_error("prm[%d]: the learned coarse step is defined for the inverse flows only", i);
+    if (p.coarse == FM_COARSE_LEARNED && f->impl.inst[i].kind != FM_FLOW_INV_HOMOTOPY &&
+        f->impl.inst[i].kind != FM_FLOW_INV_STEADY) {
+      set_error("prm[%d]: the learned coarse step is defined for the two quadratic inverse flows only", i);
       return FM_ERR_UNSUPPORTED;
     }
   }

@@ -441,6 +441,50 @@ fm_status Flow::gemm_groups(int epi, std::vector<GItem>& items, const std::vecto
   return FM_OK;
 }
 
+// Flows whose stage field takes two products (first P = B Y, then Y P).
+static bool two_products(int kind) { return kind == FM_FLOW_INV_HOMOTOPY || kind == FM_FLOW_INV_STEADY; }
+
+// The stage-field product of item g (reading stage operand y, and P = B y
+// for the two-product flows): k = s0 (a b) + s1 E + s3 I per flow kind.
+static void field_item(GItem& g, const Inst& in, void* y, void* p) {
+  switch (in.kind) {
+    case FM_FLOW_INV_HOMOTOPY:  // k = -Y (M Y)
+      g.a = y;
+      g.b = p;
+      g.s[0] = -1.0;
+      g.flags = F_E_NONE;
+      break;
+    case FM_FLOW_INV_STEADY:  // k = Y - Y (A Y)
+      g.a = y;
+      g.b = p;
+      g.s[0] = -1.0;
+      g.s[1] = 1.0;
+      g.in0 = y;
+      g.flags = 0;
+      break;
+    case FM_FLOW_SQRT_STEADY:  // k = A - Y Y
+      g.a = y;
+      g.b = y;
+      g.s[0] = -1.0;
+      g.s[1] = 1.0;
+      g.in0 = in.A64;
+      g.flags = F_E_F64;
+      break;
+    case FM_FLOW_EXP:  // k = A Y
+      g.a = in.Bop;
+      g.b = y;
+      g.s[0] = 1.0;
+      g.flags = F_E_NONE;
+      break;
+    default:  // FM_FLOW_INV_LINEAR: k = I - A Y
+      g.a = in.Bop;
+      g.b = y;
+      g.s[0] = -1.0;
+      g.s[3] = 1.0;
+      g.flags = F_E_NONE;
+  }
+}
+
 static GItem blank_item(const Inst& in, int i) {
   GItem it;
   memset(&it, 0, sizeof it);
@@ -455,17 +499,25 @@ static GItem blank_item(const Inst& in, int i) {
 // slot.x; slot.ya must hold op(x) on entry.  One grouped launch per product:
 // stage s reads Y from ya (s odd) or yb (s even) and writes the next stage
 // operand to the other buffer, so after 4 stages Y is back in ya.
-fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStream_t st) {
+fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int method, hipStream_t st) {
   if (slots.empty() || steps <= 0) return FM_OK;
   // Build the 8 item lists once; they are identical for every step.
+  // RK4: one unit = one step of 4 stages (operands ya -> yb -> ya -> yb -> ya).
+  // Forward Euler: one unit = two steps (ya -> yb -> ya); an odd step count
+  // ends with one more step on the first list (result operand in yb).
+  const bool euler = method == FM_FINE_EULER;
+  const int nst = euler ? 2 : 4;
+  const int units = euler ? steps / 2 : steps;
+  const bool tail = euler && (steps % 2 == 1);
+  const int fepi = euler ? EPI_EULER : EPI_RK4;
   std::vector<GItem> l1[4], l2[4];
   std::vector<int> i1[4], i2[4];
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < nst; ++s) {
     for (const FineSlot& sl : slots) {
       const Inst& in = inst[sl.inst];
       void* ycur = (s % 2 == 0) ? sl.ya : sl.yb;
       void* ynext = (s % 2 == 0) ? sl.yb : sl.ya;
-      if (in.kind != FM_FLOW_SQRT_STEADY) {
+      if (two_products(in.kind)) {
         GItem g = blank_item(in, sl.inst);
         g.a = in.Bop;
         g.b = ycur;
@@ -476,32 +528,12 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
         i1[s].push_back(sl.inst);
       }
       GItem g = blank_item(in, sl.inst);
-      g.a = ycur;
+      field_item(g, in, ycur, sl.p);
       g.out0 = ynext;
-      g.out1 = sl.kacc;
+      g.out1 = euler ? (void*)sl.x : sl.kacc;
       g.x = sl.x;
       g.stage = s + 1;
       g.s[2] = sl.h;
-      switch (in.kind) {
-        case FM_FLOW_INV_HOMOTOPY:  // k = -Y (M Y)
-          g.b = sl.p;
-          g.s[0] = -1.0;
-          g.flags = F_E_NONE;
-          break;
-        case FM_FLOW_INV_STEADY:  // k = Y - Y (A Y)
-          g.b = sl.p;
-          g.s[0] = -1.0;
-          g.s[1] = 1.0;
-          g.in0 = ycur;
-          g.flags = 0;
-          break;
-        default:  // k = A - Y Y
-          g.b = ycur;
-          g.s[0] = -1.0;
-          g.s[1] = 1.0;
-          g.in0 = in.A64;
-          g.flags = F_E_F64;
-      }
       l2[s].push_back(g);
       i2[s].push_back(sl.inst);
     }
@@ -521,7 +553,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
   {
     // every list below is launched `steps` times: no ring reset in between
     size_t need = 0;
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < nst; ++s)
       need += (l1[s].size() + l2[s].size()) * (sizeof(GItem) + sizeof(int)) + 8 * 512;
     FM_TRY(reserve_ring(need, st));
   }
@@ -562,9 +594,11 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
     }
     return FM_OK;
   };
-  for (int s = 0; s < 4; ++s) {
+  size_t first_stage_end = 0;  // launches of the first list (the Euler tail)
+  for (int s = 0; s < nst; ++s) {
     FM_TRY(prepare(l1[s], i1[s], EPI_AFFINE));
-    FM_TRY(prepare(l2[s], i2[s], EPI_RK4));
+    FM_TRY(prepare(l2[s], i2[s], fepi));
+    if (s == 0) first_stage_end = seq.size();
   }
   int phase_ev = -1;
   if (timing) {
@@ -573,8 +607,16 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
     if (!e0 || !e1) timing = false;
     else FM_HIP(hipEventRecord(e0, st));
   }
-  if (use_graph && cap_stream && !timing && steps > 1) {
-    // capture the launches of one RK4 step once, replay the graph `steps` times
+  auto launch_tail = [&]() -> fm_status {
+    if (tail)
+      for (size_t j = 0; j < first_stage_end; ++j) {
+        const Launch& L = seq[j];
+        FM_HIP(launch_gemm(L.cfg, L.epi, L.items, L.ts, L.n, L.total, L.grid, nullptr, st));
+      }
+    return FM_OK;
+  };
+  if (use_graph && cap_stream && !timing && units > 1) {
+    // capture the launches of one unit once, replay the graph for every unit
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     FM_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
@@ -593,12 +635,12 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
     pending_graph.push_back(g);
     pending_exec.push_back(ge);
     pending_stream.push_back(st);
-    for (int step = 0; step < steps; ++step) FM_HIP(hipGraphLaunch(ge, st));
-    return FM_OK;
+    for (int u = 0; u < units; ++u) FM_HIP(hipGraphLaunch(ge, st));
+    return launch_tail();
   }
-  for (int step = 0; step < steps; ++step)
+  for (int u = 0; u < units; ++u)
     for (const Launch& L : seq) {
-      const bool rec = timing && L.epi == EPI_RK4;
+      const bool rec = timing && L.epi == fepi;
       int idx = -1;
       if (rec) {
         idx = (int)ev_used;
@@ -612,6 +654,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, hipStrea
         ev_pairs.push_back({idx, L.flops});
       }
     }
+  FM_TRY(launch_tail());
   if (timing && phase_ev >= 0) {
     FM_HIP(hipEventRecord(ev[phase_ev + 1], st));
     phase_pairs.push_back(phase_ev);
@@ -650,7 +693,7 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
       void* yout = (j % 2 == 0) ? sl.y1 : sl.y0;
       const double* x = (j == 0) ? sl.xin : sl.xout;
       if (!sl.learned) {
-        if (in.kind != FM_FLOW_SQRT_STEADY) {
+        if (two_products(in.kind)) {
           GItem g = blank_item(in, sl.inst);
           g.a = in.Bop;
           g.b = yin;
@@ -661,31 +704,11 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
           i1.push_back(sl.inst);
         }
         GItem g = blank_item(in, sl.inst);
-        g.a = yin;
+        field_item(g, in, yin, sl.p);
         g.out0 = yout;
         g.out1 = sl.xout;
         g.x = const_cast<double*>(x);
         g.s[2] = sl.h;
-        switch (in.kind) {
-          case FM_FLOW_INV_HOMOTOPY:
-            g.b = sl.p;
-            g.s[0] = -1.0;
-            g.flags = F_E_NONE;
-            break;
-          case FM_FLOW_INV_STEADY:
-            g.b = sl.p;
-            g.s[0] = -1.0;
-            g.s[1] = 1.0;
-            g.in0 = yin;
-            g.flags = 0;
-            break;
-          default:
-            g.b = yin;
-            g.s[0] = -1.0;
-            g.s[1] = 1.0;
-            g.in0 = in.A64;
-            g.flags = F_E_F64;
-        }
         l2.push_back(g);
         i2.push_back(sl.inst);
       } else {
@@ -793,7 +816,7 @@ fm_status Flow::fine_propagate(double t1, double t0, int steps, const double* co
   void* d = nullptr;
   FM_TRY(push(prep.data(), prep.size() * sizeof(PrepItem), &d, st));
   FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), dt, nullptr, st));
-  FM_TRY(run_fine(slots, steps, st));
+  FM_TRY(run_fine(slots, steps, FM_FINE_RK4, st));
   {
     std::vector<double*> dst(batch);
     std::vector<const double*> src(batch);
@@ -1121,9 +1144,9 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
       FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), dt, nullptr, st));
     }
     {
-      std::map<int, std::vector<FineSlot>> by;
-      for (auto& f : fs) by[prm[f.inst].fine_steps].push_back(f);
-      for (auto& g : by) FM_TRY(run_fine(g.second, g.first, st));
+      std::map<std::pair<int, int>, std::vector<FineSlot>> by;  // (steps, scheme)
+      for (auto& f : fs) by[{prm[f.inst].fine_steps, prm[f.inst].fine_method}].push_back(f);
+      for (auto& g : by) FM_TRY(run_fine(g.second, g.first.first, g.first.second, st));
     }
     // learned coarse: choose per slice between the learned and the Euler step
     // by their defect against F(U^k_n) (the Euler fallback), and set G_old to
@@ -1267,7 +1290,7 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
   std::vector<int> which;
   for (int i = 0; i < batch; ++i) {
     X[i] = w[i].U[prm[i].N];
-    if (ist[i] != FM_ERR_NONFINITE) which.push_back(i);
+    if (ist[i] != FM_ERR_NONFINITE && inst[i].kind != FM_FLOW_EXP) which.push_back(i);
   }
   if (stats) {
     for (int i = 0; i < batch; ++i) {

@@ -160,7 +160,7 @@ struct Flow {
                      hipStream_t st);
   fm_status ensure_hredu(size_t count);
 
-  fm_status run_fine(const std::vector<FineSlot>& slots, int steps, hipStream_t st);
+  fm_status run_fine(const std::vector<FineSlot>& slots, int steps, int method, hipStream_t st);
   fm_status run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipStream_t st);
   // coefficients for rows (problem, t, h): c = c_Euler(h) + net(t, h, mu)
   struct CoefRow {

@@ -233,6 +233,11 @@ __device__ __forceinline__ void epilogue4(const GItem& it, int64_t idx, int dpos
 #pragma unroll
       for (int e = 0; e < EV; ++e) k.v[e] += s[1] * E.v[e];
     }
+    if (s[3] != 0.0) {  // identity term of the field (dX/dt = I - A X)
+#pragma unroll
+      for (int e = 0; e < EV; ++e)
+        if (e == dpos) k.v[e] += s[3];
+    }
     const double h = s[2];
     const V4 x = gld4<double>(it.x, idx);
     V4 o;

@@ -23,9 +23,12 @@ FM_ERR_UNSUPPORTED = -5
 FM_FLOW_INV_HOMOTOPY = 1
 FM_FLOW_INV_STEADY = 2
 FM_FLOW_SQRT_STEADY = 3
+FM_FLOW_EXP = 4
+FM_FLOW_INV_LINEAR = 5
 
 FM_F64, FM_F32, FM_BF16, FM_F16, FM_BF16X3 = 0, 1, 2, 3, 4
 FM_COARSE_EULER, FM_COARSE_LEARNED = 0, 1
+FM_FINE_RK4, FM_FINE_EULER = 0, 1
 
 DTYPES = {"f64": FM_F64, "f32": FM_F32, "bf16": FM_BF16, "f16": FM_F16, "bf16x3": FM_BF16X3}
 
@@ -44,7 +47,8 @@ class fm_problem(ctypes.Structure):
 class fm_params(ctypes.Structure):
     _fields_ = [("T", ctypes.c_double), ("N", ctypes.c_int32), ("coarse_steps", ctypes.c_int32),
                 ("fine_steps", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("coarse", ctypes.c_int32),
-                ("max_refine", ctypes.c_int32), ("tol", ctypes.c_double), ("refine_tol", ctypes.c_double)]
+                ("max_refine", ctypes.c_int32), ("tol", ctypes.c_double), ("refine_tol", ctypes.c_double),
+                ("fine_method", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class fm_stats(ctypes.Structure):
@@ -148,7 +152,8 @@ def fm_parareal_solve(flow, X0, X_out, params, stream=None):
     for i, p in enumerate(params):
         prm[i] = fm_params(float(p["T"]), int(p["N"]), int(p.get("coarse_steps", 1)), int(p["fine_steps"]),
                            int(p.get("max_iter", p["N"])), int(p.get("coarse", FM_COARSE_EULER)),
-                           int(p.get("max_refine", 0)), float(p.get("tol", 0.0)), float(p.get("refine_tol", 0.0)))
+                           int(p.get("max_refine", 0)), float(p.get("tol", 0.0)), float(p.get("refine_tol", 0.0)),
+                           int(p.get("fine_method", FM_FINE_RK4)), 0)
     stats = (fm_stats * n)()
     x0 = _ptrs(X0)
     st = _check(lib.fm_parareal_solve(flow, x0, _ptrs(X_out), prm, stats, _stream(stream)))

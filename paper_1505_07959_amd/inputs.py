@@ -119,6 +119,22 @@ def nonsymmetric(n, seed, shift=2.0, spread=0.3):
     return np.ascontiguousarray(shift * np.eye(n) + spread * rng.standard_normal((n, n)) / np.sqrt(n))
 
 
+def laplacian_1d(n):
+    """The 1D Laplacian of the paper's Example 1 (Sec. 2) on n interior points
+    of (0, 1), Dirichlet ends: (n+1)^2 tridiag(-1, 2, -1) (the h^-2-scaled
+    finite-difference matrix; eigenvalues 4 (n+1)^2 sin^2(j pi / (2(n+1))))."""
+    T = 2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    return np.ascontiguousarray((n + 1) ** 2 * T)
+
+
+def laplacian_2d(m):
+    """The 5-point Laplacian on an m x m interior grid of the unit square
+    (Sec. 4, Example 5), order m^2, Dirichlet boundary, h^-2 scaled."""
+    T = 2.0 * np.eye(m) - np.eye(m, k=1) - np.eye(m, k=-1)
+    I = np.eye(m)
+    return np.ascontiguousarray((m + 1) ** 2 * (np.kron(T, I) + np.kron(I, T)))
+
+
 def perturbed_identity(n, seed, eps=0.05):
     """A starting value that does not commute with A: I + eps N(0,1)/sqrt(n)."""
     rng = np.random.default_rng(seed)

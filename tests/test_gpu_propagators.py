@@ -7,7 +7,7 @@ the library: 4 x 4 tiles of 64)."""
 import numpy as np
 import pytest
 
-from oracle import MatrixAlgebra, HOMOTOPY, STEADY_INV, SQRT, integrators
+from oracle import MatrixAlgebra, HOMOTOPY, STEADY_INV, SQRT, EXP, INV_LINEAR, integrators
 from paper_1505_07959_amd import inputs
 from tests.gpu_util import dev, host, empty, rel, say
 
@@ -25,7 +25,7 @@ def _case(kind, n, seed):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16", "bf16x3"])
-@pytest.mark.parametrize("kind", [HOMOTOPY, STEADY_INV, SQRT])
+@pytest.mark.parametrize("kind", [HOMOTOPY, STEADY_INV, SQRT, EXP, INV_LINEAR])
 @pytest.mark.parametrize("n", [200, 64])
 def test_fine_propagate_matches_oracle(dtype, kind, n):
     from paper_1505_07959_amd import fm
@@ -46,7 +46,7 @@ def test_fine_propagate_matches_oracle(dtype, kind, n):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "bf16x3"])
-@pytest.mark.parametrize("kind", [HOMOTOPY, STEADY_INV, SQRT])
+@pytest.mark.parametrize("kind", [HOMOTOPY, STEADY_INV, SQRT, EXP, INV_LINEAR])
 def test_coarse_propagate_matches_oracle(dtype, kind):
     from paper_1505_07959_amd import fm
     n = 136

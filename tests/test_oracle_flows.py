@@ -221,3 +221,16 @@ def test_linear_inverse_flow_reaches_the_inverse():
     assert np.linalg.norm(Xe - Ai) <= 1e-10 * np.linalg.norm(Ai)
     assert exact.target(INV_LINEAR, A) is not None
     assert np.allclose(exact.target(EXP, A, 0.5), (Q * np.exp(0.5 * lam)) @ Q.T, atol=1e-13)
+
+
+def test_laplacian_generators():
+    """The stencil matrices of Examples 1 and 5 against their known spectra."""
+    n = 12
+    lam = np.linalg.eigvalsh(inputs.laplacian_1d(n))
+    j = np.arange(1, n + 1)
+    want = 4 * (n + 1) ** 2 * np.sin(j * np.pi / (2 * (n + 1))) ** 2
+    assert np.allclose(lam, np.sort(want), rtol=1e-12)
+    m = 5
+    L2 = inputs.laplacian_2d(m)
+    mu = 4 * (m + 1) ** 2 * np.sin(np.arange(1, m + 1) * np.pi / (2 * (m + 1))) ** 2
+    assert np.allclose(np.linalg.eigvalsh(L2), np.sort(np.add.outer(mu, mu).ravel()), rtol=1e-12)
