@@ -191,6 +191,28 @@ fm_status fm_coarse_propagate(fm_flow f, double t_next, double t_cur, int32_t st
                               double* const* X_out, void* hip_stream);
 
 /* Release the flow and all its device memory.  NULL is accepted. */
+/* Sec. 4, Example 5, Alg. 8 (acceleration of convergence in time towards
+ * A^{-1}): for every problem of the flow, all of kind FM_FLOW_INV_LINEAR,
+ *     X_{k+1} = X_k + dt (I - A X_k + u_k),   u_{k+1} = (I - dt A) u_k,
+ *     u_0 = E,   k = 0 .. steps-1,
+ * where u_k is added only while k < accel_steps (accel_steps >= steps: at
+ * every step, as Alg. 8 is printed; a smaller value switches the accelerator
+ * off at t* = accel_steps dt, the cut-off control of Example 4).  With E = 0
+ * this is forward-Euler time marching on dX/dt = I - A X.
+ * X0, E: host arrays of `batch` device pointers to n x n FP64 row-major
+ *   matrices (leading dimension n); the array itself or an entry may be NULL
+ *   (zero matrix).  E approximates A^{-1} - X0 (the paper builds it from an
+ *   incomplete factorisation or a thresholded inverse; the caller supplies it).
+ * X_out: device n x n FP64 per problem, written with X_steps.
+ * hist: NULL, or a host array of batch * (steps / every + 1) doubles that
+ *   receives ||I - A X_k||_F (FP64 product) for k = 0, every, 2 every, ...:
+ *   hist[i * (steps / every + 1) + j] for problem i, k = j every.
+ * Products in the flow's dtype with FP64 X and u; blocks until done.
+ * Errors: FM_ERR_INVALID for dt <= 0, negative counts, every < 1 with hist,
+ * a flow of another kind or NULL X_out. */
+fm_status fm_aima(fm_flow f, const double* const* X0, const double* const* E, double dt, int32_t steps,
+                  int32_t accel_steps, int32_t every, double* const* X_out, double* hist, void* hip_stream);
+
 void fm_destroy(fm_flow f);
 
 /* Thread-local message of the last error (empty string if none). */

@@ -154,6 +154,24 @@ fm_status fm_coarse_propagate(fm_flow f, double t_next, double t_cur, int32_t st
   return f->impl.coarse_propagate(t_next, t_cur, steps, coarse, X_in, X_out, (hipStream_t)hip_stream);
 }
 
+fm_status fm_aima(fm_flow f, const double* const* X0, const double* const* E, double dt, int32_t steps,
+                  int32_t accel_steps, int32_t every, double* const* X_out, double* hist, void* hip_stream) {
+  fm::clear_error();
+  fm_status s = check_flow(f);
+  if (s != FM_OK) return s;
+  if ((s = check_ptrs(f, (const void* const*)X_out, "X_out")) != FM_OK) return s;
+  if (!(dt > 0) || !std::isfinite(dt) || steps < 0 || accel_steps < 0 || (hist && every < 1)) {
+    set_error("fm_aima: need dt > 0, steps >= 0, accel_steps >= 0 and every >= 1 with hist");
+    return FM_ERR_INVALID;
+  }
+  for (int i = 0; i < f->impl.batch; ++i)
+    if (f->impl.inst[i].kind != FM_FLOW_INV_LINEAR) {
+      set_error("fm_aima: problem %d is not an FM_FLOW_INV_LINEAR flow", i);
+      return FM_ERR_INVALID;
+    }
+  return f->impl.aima(X0, E, dt, steps, accel_steps, every, X_out, hist, (hipStream_t)hip_stream);
+}
+
 void fm_destroy(fm_flow f) {
   if (!f) return;
   int cur = 0;

@@ -1320,6 +1320,215 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
   return worst;
 }
 
+// ------------------------------------------------- accelerated marching
+// Alg. 8 (Sec. 4, Example 5) for every problem of the flow:
+//   X_{k+1} = X_k + dt (I - A X_k + u_k),  u_{k+1} = u_k - dt A u_k,  u_0 = E,
+// with u applied while k < accel_steps.  One grouped launch per step holds
+// the product A X_k (Euler epilogue adding I and u_k) and A u_k (Euler
+// epilogue); X is updated in place (each element by its own thread), u and
+// both product operands ping-pong between two buffers because the epilogue
+// of one tile must not overwrite what another tile still reads.  Every
+// `every` steps R = I - A X is formed in FP64 and ||R||_F^2 reduced into a
+// device table read back once at the end.
+fm_status Flow::aima(const double* const* X0, const double* const* E, double step, int steps, int accel_steps,
+                     int every, double* const* Xout, double* hist, hipStream_t st) {
+  struct AW {
+    double *x, *u[2], *r;
+    void *xo[2], *uo[2];
+  };
+  std::vector<AW> b(batch);
+  const int nh = hist ? steps / every + 1 : 0;
+  double *hdev = nullptr, *hpart = nullptr;
+  constexpr int HBLK = 16;
+  for (int pass = 0; pass < 2; ++pass) {
+    prop.measuring = (pass == 0);
+    prop.used = 0;
+    for (int i = 0; i < batch; ++i) {
+      const size_t np2 = (size_t)inst[i].np * inst[i].np;
+      b[i].x = (double*)prop.take(np2 * 8);
+      b[i].u[0] = (double*)prop.take(np2 * 8);
+      b[i].u[1] = (double*)prop.take(np2 * 8);
+      b[i].r = hist ? (double*)prop.take(np2 * 8) : nullptr;
+      for (int q = 0; q < 2; ++q) {
+        b[i].xo[q] = prop.take(np2 * dt_size(dt));
+        b[i].uo[q] = prop.take(np2 * dt_size(dt));
+      }
+    }
+    hdev = (double*)prop.take(sizeof(double) * (size_t)std::max(1, batch * nh));
+    hpart = (double*)prop.take(sizeof(double) * (size_t)batch * HBLK);
+    if (pass == 0) FM_TRY(prop.reserve(prop.used));
+  }
+  FM_HIP(hipStreamSynchronize(st));
+  release_graphs();
+  ring.reset();
+  // initial values (absent: zero), op-dtype copies of X_0 and u_0
+  for (int i = 0; i < batch; ++i) {
+    const size_t np2 = (size_t)inst[i].np * inst[i].np;
+    FM_HIP(hipMemsetAsync(b[i].x, 0, np2 * 8, st));
+    FM_HIP(hipMemsetAsync(b[i].u[0], 0, np2 * 8, st));
+  }
+  {
+    std::vector<double*> dx, du;
+    std::vector<const double*> sx, su;
+    for (int i = 0; i < batch; ++i) {
+      dx.push_back(b[i].x);
+      sx.push_back(X0 ? X0[i] : nullptr);
+      du.push_back(b[i].u[0]);
+      su.push_back(E ? E[i] : nullptr);
+    }
+    // pad_copy of a subset: copy the present entries one batch at a time
+    std::vector<PadItem> it;
+    for (int i = 0; i < batch; ++i) {
+      if (sx[i]) it.push_back(PadItem{dx[i], sx[i], inst[i].n, inst[i].np});
+      if (su[i]) it.push_back(PadItem{du[i], su[i], inst[i].n, inst[i].np});
+    }
+    if (!it.empty()) {
+      void* d = nullptr;
+      FM_TRY(push(it.data(), it.size() * sizeof(PadItem), &d, st));
+      FM_HIP(launch_pad_copy((const PadItem*)d, (int)it.size(), 1, st));
+    }
+    std::vector<PrepItem> prep;
+    for (int i = 0; i < batch; ++i) {
+      const int64_t cnt = (int64_t)inst[i].np * inst[i].np;
+      prep.push_back(PrepItem{b[i].x, nullptr, b[i].xo[0], cnt, i, 0});
+      prep.push_back(PrepItem{b[i].u[0], nullptr, b[i].uo[0], cnt, i, 0});
+    }
+    void* d = nullptr;
+    FM_TRY(push(prep.data(), prep.size() * sizeof(PrepItem), &d, st));
+    FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), dt, nullptr, st));
+  }
+  // launch lists: [accelerated?][parity]; residual list
+  struct L {
+    GemmCfg cfg;
+    const GItem* items;
+    const int* ts;
+    int n, total, grid;
+  };
+  auto prepare = [&](std::vector<GItem>& items, bool f64, std::vector<L>& out) -> fm_status {
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (size_t j = 0; j < items.size(); ++j) {
+      const GemmCfg& c = f64 ? inst[items[j].inst].cfg64 : inst[items[j].inst].cfg;
+      groups[{c.bm, c.bk}].push_back((int)j);
+    }
+    for (auto& g : groups) {
+      L l;
+      l.cfg.dt = f64 ? DT_F64 : dt;
+      l.cfg.bm = g.first.first;
+      l.cfg.bk = g.first.second;
+      std::vector<GItem> sub;
+      std::vector<int> ts(1, 0);
+      int total = 0;
+      for (int j : g.second) {
+        sub.push_back(items[j]);
+        const int tpn = items[j].np / l.cfg.bm;
+        total += tpn * tpn;
+        ts.push_back(total);
+      }
+      void *di = nullptr, *dts = nullptr;
+      FM_TRY(push(sub.data(), sub.size() * sizeof(GItem), &di, st));
+      FM_TRY(push(ts.data(), ts.size() * sizeof(int), &dts, st));
+      l.items = (const GItem*)di;
+      l.ts = (const int*)dts;
+      l.n = (int)sub.size();
+      l.total = total;
+      l.grid = std::min(total, gemm_max_grid(l.cfg));
+      out.push_back(l);
+    }
+    return FM_OK;
+  };
+  std::vector<L> step_l[2][2], res_l;
+  for (int acc = 0; acc < 2; ++acc)
+    for (int par = 0; par < 2; ++par) {
+      std::vector<GItem> items;
+      for (int i = 0; i < batch; ++i) {
+        const Inst& in = inst[i];
+        GItem g = blank_item(in, i);  // X_{k+1} = X_k + dt (I - A X_k [+ u_k])
+        g.a = in.Bop;
+        g.b = b[i].xo[par];
+        g.s[0] = -1.0;
+        g.s[2] = step;
+        g.s[3] = 1.0;
+        g.x = b[i].x;
+        g.out1 = b[i].x;
+        g.out0 = b[i].xo[par ^ 1];
+        if (acc) {
+          g.in0 = b[i].u[par];
+          g.s[1] = 1.0;
+          g.flags = F_E_F64;
+        } else {
+          g.flags = F_E_NONE;
+        }
+        items.push_back(g);
+        if (acc) {
+          GItem q = blank_item(in, i);  // u_{k+1} = u_k - dt A u_k
+          q.a = in.Bop;
+          q.b = b[i].uo[par];
+          q.s[0] = -1.0;
+          q.s[2] = step;
+          q.flags = F_E_NONE;
+          q.x = b[i].u[par];
+          q.out1 = b[i].u[par ^ 1];
+          q.out0 = b[i].uo[par ^ 1];
+          items.push_back(q);
+        }
+      }
+      FM_TRY(prepare(items, false, step_l[acc][par]));
+    }
+  const DotItem* dots_dev = nullptr;  // per evaluation j: batch items at dots_dev + j * batch
+  if (hist) {
+    std::vector<GItem> items;
+    for (int i = 0; i < batch; ++i) {
+      GItem g = blank_item(inst[i], i);  // R = I - A X in FP64
+      g.a = inst[i].A64;
+      g.b = b[i].x;
+      g.s[0] = -1.0;
+      g.s[2] = 1.0;
+      g.flags = F_E_NONE | F_OUT0_F64;
+      g.out0 = b[i].r;
+      items.push_back(g);
+    }
+    FM_TRY(prepare(items, true, res_l));
+    std::vector<DotItem> it;
+    for (int j = 0; j < nh; ++j)
+      for (int i = 0; i < batch; ++i)
+        it.push_back(DotItem{b[i].r, b[i].r, (int64_t)inst[i].np * inst[i].np, i * nh + j, 0, nullptr});
+    void* d = nullptr;
+    FM_TRY(push(it.data(), it.size() * sizeof(DotItem), &d, st));
+    dots_dev = (const DotItem*)d;
+  }
+  auto residual = [&](int j) -> fm_status {
+    for (const L& l : res_l) FM_HIP(launch_gemm(l.cfg, EPI_AFFINE, l.items, l.ts, l.n, l.total, l.grid, nullptr, st));
+    FM_HIP(launch_dots(dots_dev + (size_t)j * batch, batch, hpart, HBLK, hdev, st));
+    return FM_OK;
+  };
+  // the X and u operands alternate buffers every step (the u buffers stay in
+  // step with X even after the cut-off, where they are no longer read)
+  for (int k = 0; k < steps; ++k) {
+    if (hist && k % every == 0) FM_TRY(residual(k / every));
+    const int acc = k < accel_steps ? 1 : 0;
+    for (const L& l : step_l[acc][k & 1])
+      FM_HIP(launch_gemm(l.cfg, EPI_EULER, l.items, l.ts, l.n, l.total, l.grid, nullptr, st));
+  }
+  if (hist && steps % every == 0) FM_TRY(residual(steps / every));
+  {
+    std::vector<double*> dst(batch);
+    std::vector<const double*> src(batch);
+    for (int i = 0; i < batch; ++i) {
+      dst[i] = Xout[i];
+      src[i] = b[i].x;
+    }
+    FM_TRY(pad_copy(dst, src, 0, st));
+  }
+  if (hist) {
+    std::vector<double> h((size_t)batch * nh);
+    FM_HIP(hipMemcpyAsync(h.data(), hdev, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    FM_HIP(hipStreamSynchronize(st));
+    for (size_t j = 0; j < h.size(); ++j) hist[j] = std::sqrt(h[j]);
+  }
+  FM_HIP(hipStreamSynchronize(st));
+  return FM_OK;
+}
+
 // ----------------------------------------------------------- refinement
 // Inverse flows: R = I - A X, X <- X + X R (Newton-Schulz, I - A X+ = R^2).
 // Square root: R = A - X^2, X <- X + H with X H + H X = R (full Newton step),

@@ -76,6 +76,9 @@ def _load():
     lib.fm_flow_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(fm_problem), ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_char_p, P]
     lib.fm_parareal_solve.argtypes = [P, PP, PP, ctypes.POINTER(fm_params), ctypes.POINTER(fm_stats), P]
+    lib.fm_aima.argtypes = [P, PP, PP, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, PP,
+                            ctypes.POINTER(ctypes.c_double), P]
+    lib.fm_aima.restype = ctypes.c_int
     lib.fm_fine_propagate.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, PP, PP, P]
     lib.fm_coarse_propagate.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                         PP, PP, P]
@@ -158,6 +161,20 @@ def fm_parareal_solve(flow, X0, X_out, params, stream=None):
     x0 = _ptrs(X0)
     st = _check(lib.fm_parareal_solve(flow, x0, _ptrs(X_out), prm, stats, _stream(stream)))
     return st, [s.as_dict() for s in stats]
+
+
+def fm_aima(flow, X0, E, dt, steps, X_out, accel_steps=None, every=0, stream=None):
+    """Alg. 8; X0 / E: list of tensors or None (zero).  Returns the residual
+    history (list per problem) when every > 0, else None."""
+    n = len(X_out)
+    nh = steps // every + 1 if every > 0 else 0
+    hist = (ctypes.c_double * max(1, n * nh))() if every > 0 else None
+    _check(lib.fm_aima(flow, _ptrs(X0), _ptrs(E), float(dt), int(steps),
+                       int(steps if accel_steps is None else accel_steps), int(every), _ptrs(X_out),
+                       hist, _stream(stream)))
+    if hist is None:
+        return None
+    return [list(hist[i * nh:(i + 1) * nh]) for i in range(n)]
 
 
 def fm_fine_propagate(flow, t_next, t_cur, steps, X_in, X_out, stream=None):
