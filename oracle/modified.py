@@ -1,0 +1,119 @@
+"""Modified (subspace-enhanced) parareal for linear matrix flows (Sec. 3,
+Alg. 2-4) -- test infrastructure only.
+
+Definitions of Sec. 3:
+* Frobenius inner product <A, B>_F = tr(B^T A); a family is F-orthonormal when
+  it is orthonormal for it.
+* The diamond product of two families A = [A_1..A_p], B = [B_1..B_l] is the
+  p x l matrix A^T <> B with entries <A_i, B_j>_F.
+* globalQR (Alg. 2): Gram-Schmidt of Z_1..Z_k in the Frobenius inner product,
+  in the modified order of Alg. 2 (each new block is projected against every
+  accepted one in turn); a block whose remaining norm r_ii vanishes is
+  eliminated.  Z_i = sum_j R[j, i] Q_j.  Readings: the normalisation written
+  as <Q_i, Q_1>_F = 1 is <Q_i, Q_i>_F = 1 (a garble); in floating point r_ii
+  counts as zero when r_ii <= drop_tol ||Z_i||_F.
+* Projection onto span{Q}: P Y = sum_i alpha_i Q_i with (alpha_i) = Q^T <> Y.
+
+Alg. 3 (linear homogeneous U' = B U): Step 0 is the coarse sweep of Alg. 1.
+Step k+1 enlarges S^k = span(S^{k-1} u {U^k_n, n = 0..N}) by completing the
+F-orthonormal basis of S^{k-1} with globalQR, computes F(T_{n+1}, T_n, Q_j)
+for the new basis blocks, and sweeps
+    U^{k+1}_{n+1} = F(T_{n+1}, T_n, P U^{k+1}_n) + G(T_{n+1}, T_n, (I - P) U^{k+1}_n),
+with F(P U) = sum_i alpha_i F(Q_i) by linearity.
+Alg. 4 (affine, U' = B U + c): F(0), G(0) are computed first (Step -1);
+F(P U) = sum_i alpha_i (F(Q_i) - F(0)) + F(0) and the update subtracts G(0).
+
+Stopping rule as for Alg. 1 (reading): the relative increment, max_iter, or
+k = N; by induction U^k_n = F^n(u0) for n <= k here too, since U^k_n lies in
+S^k and is reproduced by the projection.
+"""
+
+import numpy as np
+
+DROP_TOL = 1e-10
+
+
+def diamond(As, Bs, inner):
+    """A^T <> B for families As, Bs (Sec. 3 definition)."""
+    return np.array([[inner(a, b) for b in Bs] for a in As])
+
+
+def global_qr(Z, inner, norm, prefix=(), drop_tol=DROP_TOL):
+    """Alg. 2 on the blocks Z, continuing an F-orthonormal `prefix` (kept as
+    is: the basis of S^{k-1} is completed, not recomputed).
+
+    Returns (Q, R, kept): Q = prefix + accepted new blocks; R[j, i] the
+    coefficient of Q_j in Z_i (rows for every block of Q); kept[i] tells
+    whether Z_i contributed a new block."""
+    Q = list(prefix)
+    coeffs = []
+    kept = []
+    for z in Z:
+        q = z
+        r = {}
+        for j, qj in enumerate(Q):
+            r[j] = inner(q, qj)
+            q = q - r[j] * qj
+        rii = norm(q)
+        nz = norm(z)
+        if rii > drop_tol * nz and rii > 0:
+            r[len(Q)] = rii
+            Q.append(q / rii)
+            kept.append(True)
+        else:
+            kept.append(False)
+        coeffs.append(r)
+    R = np.zeros((len(Q), len(Z)))
+    for i, r in enumerate(coeffs):
+        for j, v in r.items():
+            R[j, i] = v
+    return Q, R, kept
+
+
+def modified_parareal(F, G, u0, N, max_iter, tol, norm, inner, affine=False, drop_tol=DROP_TOL):
+    """Run Alg. 3 (affine=False) or Alg. 4 (affine=True).
+
+    F(n, x), G(n, x): fine and coarse propagation over slice n.
+    Returns dict: U (final iterates), iters, increments, basis size per
+    iteration."""
+    zero = 0 * u0
+    F0 = [F(n, zero) for n in range(N)] if affine else None   # Step -1
+    G0 = [G(n, zero) for n in range(N)] if affine else None
+    U = [u0]
+    for n in range(N):
+        U.append(G(n, U[n]))
+    Q = []
+    FQ = []          # FQ[j][n] = F(n, Q_j)
+    increments, sizes = [], []
+    k = 0
+    while k < max_iter and k < N:
+        Q, _, kept = global_qr(U, inner, norm, prefix=Q, drop_tol=drop_tol)
+        for q in Q[len(FQ):]:
+            FQ.append([F(n, q) for n in range(N)])          # the parallel part
+        sizes.append(len(Q))
+        U_new = [u0]
+        for n in range(N):
+            x = U_new[n]
+            alpha = [inner(x, q) for q in Q]
+            PU = zero
+            FPU = zero
+            for a, q, fq in zip(alpha, Q, FQ):
+                PU = PU + a * q
+                FPU = FPU + a * ((fq[n] - F0[n]) if affine else fq[n])
+            if affine:
+                FPU = FPU + F0[n]
+            GR = G(n, x - PU)
+            if affine:
+                GR = GR - G0[n]
+            U_new.append(FPU + GR)
+        inc = 0.0
+        for n in range(1, N + 1):
+            d = norm(U_new[n] - U[n])
+            s = norm(U_new[n])
+            inc = max(inc, d / s if s > 0 else d)
+        U = U_new
+        k += 1
+        increments.append(inc)
+        if inc <= tol:
+            break
+    return {"U": U, "iters": k, "increments": increments, "sizes": sizes}

@@ -1,0 +1,96 @@
+"""Pins for the oracle's modified parareal, globalQR and diamond product
+(Sec. 3, Alg. 2-4) (CPU only)."""
+
+import numpy as np
+
+from oracle import MatrixAlgebra, EXP, INV_LINEAR, integrators, parareal, modified
+from paper_1505_07959_amd import inputs
+
+
+def _fro(x):
+    return float(np.sqrt(np.sum(x * x)))
+
+
+def _inner(a, b):
+    return float(np.sum(a * b))
+
+
+def test_diamond_properties():
+    """Sec. 3 proposition: s = 1 gives A^T B; X^T <> X = ||X||_F^2; an
+    F-orthonormal family has Q^T <> Q = I."""
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((5, 3))
+    B = rng.standard_normal((5, 4))
+    D = modified.diamond([A[:, [i]] for i in range(3)], [B[:, [j]] for j in range(4)], _inner)
+    assert np.allclose(D, A.T @ B, atol=1e-14)
+    X = rng.standard_normal((4, 4))
+    assert abs(modified.diamond([X], [X], _inner)[0, 0] - np.linalg.norm(X) ** 2) < 1e-12
+
+
+def test_global_qr_factorisation_and_elimination():
+    """Z = Q (R (x) I): every block is reproduced from the basis; the basis is
+    F-orthonormal; a block dependent on earlier ones is eliminated; the
+    result equals numpy's QR of the vectorised blocks up to signs."""
+    rng = np.random.default_rng(1)
+    Z = [rng.standard_normal((3, 3)) for _ in range(4)]
+    Z.insert(2, 2.0 * Z[0] - 0.5 * Z[1])          # dependent
+    Q, R, kept = modified.global_qr(Z, _inner, _fro)
+    assert kept == [True, True, False, True, True] and len(Q) == 4
+    for i, z in enumerate(Z):
+        assert np.linalg.norm(z - sum(R[j, i] * Q[j] for j in range(len(Q)))) < 1e-12
+    assert np.allclose(modified.diamond(Q, Q, _inner), np.eye(4), atol=1e-13)
+    M = np.stack([z.ravel() for z in Z if z is not Z[2]], axis=1)
+    q, r = np.linalg.qr(M)
+    for j in range(4):
+        assert np.allclose(np.abs(q[:, j]), np.abs(Q[j].ravel()), atol=1e-12)
+
+
+def _setup(kind, n=4, N=8, S=10, T=1.0):
+    A = inputs.nonsymmetric(n, 5, shift=-0.5 if kind == EXP else 1.0, spread=0.6)
+    alg = MatrixAlgebra(n)
+    t = [i * T / N for i in range(N + 1)]
+    F = lambda i, x: integrators.fine(alg, kind, A, x, t[i + 1], t[i], S)
+    G = lambda i, x: integrators.coarse(alg, kind, A, x, t[i + 1], t[i], 1)
+    X0 = inputs.perturbed_identity(n, 6, eps=0.3)
+    serial = [X0]
+    for i in range(N):
+        serial.append(F(i, serial[-1]))
+    return A, F, G, X0, serial
+
+
+def test_scalar_problem_is_exact_after_one_iteration():
+    """1 x 1 matrices: S^0 already spans the whole space, P = I, and one
+    iteration reproduces the serial fine solution."""
+    for kind in (EXP, INV_LINEAR):
+        A, F, G, X0, serial = _setup(kind, n=1)
+        out = modified.modified_parareal(F, G, X0, 8, 1, 0.0, _fro, _inner, affine=(kind == INV_LINEAR))
+        for u, s in zip(out["U"], serial):
+            assert abs(u[0, 0] - s[0, 0]) <= 1e-14 * abs(s[0, 0])
+
+
+def test_exactness_and_full_space():
+    """U^k_n = F^n(u0) for n <= k; once the basis spans all 16 directions of
+    4 x 4 matrices the sweep is the serial fine solution."""
+    for kind in (EXP, INV_LINEAR):
+        A, F, G, X0, serial = _setup(kind)
+        for K in (1, 2, 3):
+            out = modified.modified_parareal(F, G, X0, 8, K, 0.0, _fro, _inner, affine=(kind == INV_LINEAR))
+            for n in range(K + 1):
+                assert _fro(out["U"][n] - serial[n]) <= 1e-12 * _fro(serial[n])
+        out = modified.modified_parareal(F, G, X0, 8, 8, 0.0, _fro, _inner, affine=(kind == INV_LINEAR))
+        assert out["sizes"][-1] <= 16
+        full = [k for k, s in enumerate(out["sizes"]) if s == 16]
+        if full:
+            k = full[0] + 1
+            assert max(_fro(u - s) / _fro(s) for u, s in zip(out["U"], serial)) <= 1e-11
+
+
+def test_faster_than_classical():
+    """The paper's observation (Sec. 3, cosine example): on a linear problem
+    the modified algorithm needs fewer iterations than Alg. 1 to a tolerance."""
+    A, F, G, X0, serial = _setup(EXP, n=6, N=10, S=20)
+    tol = 1e-10
+    cl = parareal.parareal(F, G, X0, 10, 10, tol, _fro)
+    md = modified.modified_parareal(F, G, X0, 10, 10, tol, _fro, _inner)
+    assert md["iters"] < cl["iters"]
+    assert max(_fro(u - s) / _fro(s) for u, s in zip(md["U"], serial)) < 1e-9
