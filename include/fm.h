@@ -80,6 +80,20 @@ typedef enum {
                              per-slice fallback to Euler (see fm_params)    */
 } fm_coarse;
 
+/* Parareal variant.  FM_PARAREAL_MODIFIED is Alg. 3 (linear homogeneous,
+ * FM_FLOW_EXP) or Alg. 4 (linear affine, FM_FLOW_INV_LINEAR) of Sec. 3: the
+ * iterates U^k_0..U^k_N enlarge an F-orthonormal basis (globalQR, Alg. 2;
+ * Frobenius inner products, a block whose remaining norm is <= 1e-7 of its
+ * own is dropped: below that its direction is dominated by rounding), the fine propagator runs on the new basis blocks only (in
+ * parallel; the flows are autonomous and the slices uniform, so one fine
+ * propagation per block serves every slice), and the sweep is
+ *   U^{k+1}_{n+1} = F(P U^{k+1}_n) + G((I - P) U^{k+1}_n) [- G(0)],
+ * F(P U) from the stored fine images by linearity.  Stopping rule, stats and
+ * refinement as for Alg. 1.  The basis holds at most (max_iter + 1)(N + 1)
+ * and n^2 blocks (two FP64 n x n matrices each); every problem of a batch
+ * must use the same variant; coarse must be FM_COARSE_EULER. */
+typedef enum { FM_PARAREAL_CLASSICAL = 0, FM_PARAREAL_MODIFIED = 1 } fm_variant;
+
 /* Fine propagator F. */
 typedef enum {
   FM_FINE_RK4 = 0,    /* classical four-stage Runge-Kutta steps */
@@ -117,7 +131,7 @@ typedef struct {
   double tol;            /* >= 0 */
   double refine_tol;     /* >= 0 */
   int32_t fine_method;   /* fm_fine */
-  int32_t reserved;      /* must be 0 */
+  int32_t variant;       /* fm_variant */
 } fm_params;
 
 typedef struct {
@@ -140,6 +154,9 @@ typedef struct {
   double fine_ms;          /* their summed duration, milliseconds */
   double fine_flops;       /* their algorithmic flops: 2 n^3 per problem-slice */
   double fine_phase_ms;    /* duration of the whole batched fine phases */
+  int32_t basis_size;      /* FM_PARAREAL_MODIFIED: blocks in the basis at
+                              the end (0 for the classical variant) */
+  int32_t reserved;
 } fm_stats;
 
 /*

@@ -11,7 +11,17 @@ Definitions of Sec. 3:
   accepted one in turn); a block whose remaining norm r_ii vanishes is
   eliminated.  Z_i = sum_j R[j, i] Q_j.  Readings: the normalisation written
   as <Q_i, Q_1>_F = 1 is <Q_i, Q_i>_F = 1 (a garble); in floating point r_ii
-  counts as zero when r_ii <= drop_tol ||Z_i||_F.
+  counts as zero when r_ii <= drop_tol ||Z_i||_F, drop_tol = 1e-7: the
+  iterates form a Krylov-like sequence whose remainders shrink geometrically,
+  and a block kept with remainder rho carries a rounding error of order
+  eps / rho, so smaller remainders would make the basis (not the method's
+  consistency) depend on the summation order; what they would carry goes
+  through the coarse propagator instead.  The projection loop of Alg. 2 is
+  run twice for every block: the proposition after Alg. 2 states that the
+  result is F-orthonormal, which one Gram-Schmidt pass does not deliver in
+  FP64 on these nearly dependent iterates (one pass left the converged
+  modified iterate 3e-8 away from the serial fine solution, two passes 1e-12
+  on the same case); the coefficients r_ji are the sums of both passes.
 * Projection onto span{Q}: P Y = sum_i alpha_i Q_i with (alpha_i) = Q^T <> Y.
 
 Alg. 3 (linear homogeneous U' = B U): Step 0 is the coarse sweep of Alg. 1.
@@ -30,7 +40,7 @@ S^k and is reproduced by the projection.
 
 import numpy as np
 
-DROP_TOL = 1e-10
+DROP_TOL = 1e-7
 
 
 def diamond(As, Bs, inner):
@@ -51,9 +61,11 @@ def global_qr(Z, inner, norm, prefix=(), drop_tol=DROP_TOL):
     for z in Z:
         q = z
         r = {}
-        for j, qj in enumerate(Q):
-            r[j] = inner(q, qj)
-            q = q - r[j] * qj
+        for _ in range(2):                   # reading M1: the projections twice
+            for j, qj in enumerate(Q):
+                c = inner(q, qj)
+                r[j] = r.get(j, 0.0) + c
+                q = q - c * qj
         rii = norm(q)
         nz = norm(z)
         if rii > drop_tol * nz and rii > 0:

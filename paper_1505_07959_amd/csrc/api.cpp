@@ -99,10 +99,22 @@ fm_status fm_parareal_solve(fm_flow f, const double* const* X0, double* const* X
     if (!(p.T > 0) || !std::isfinite(p.T) || p.N < 1 || p.N > 4096 || p.coarse_steps < 1 || p.fine_steps < 1 ||
         p.max_iter < 0 || p.max_refine < 0 || !(p.tol >= 0) || !(p.refine_tol >= 0) ||
         (p.coarse != FM_COARSE_EULER && p.coarse != FM_COARSE_LEARNED) ||
-        (p.fine_method != FM_FINE_RK4 && p.fine_method != FM_FINE_EULER) || p.reserved != 0) {
+        (p.fine_method != FM_FINE_RK4 && p.fine_method != FM_FINE_EULER) ||
+        (p.variant != FM_PARAREAL_CLASSICAL && p.variant != FM_PARAREAL_MODIFIED)) {
       set_error("prm[%d]: need T > 0, 1 <= N <= 4096, steps >= 1, max_iter >= 0, tol >= 0, known coarse and "
-                "fine schemes, reserved == 0", i);
+                "fine schemes and a known variant", i);
       return FM_ERR_INVALID;
+    }
+    if (p.variant != prm[0].variant) {
+      set_error("prm[%d]: every problem of a batch must use the same parareal variant", i);
+      return FM_ERR_UNSUPPORTED;
+    }
+    if (p.variant == FM_PARAREAL_MODIFIED &&
+        ((f->impl.inst[i].kind != FM_FLOW_EXP && f->impl.inst[i].kind != FM_FLOW_INV_LINEAR) ||
+         p.coarse != FM_COARSE_EULER)) {
+      set_error("prm[%d]: the modified parareal needs a linear flow (FM_FLOW_EXP, FM_FLOW_INV_LINEAR) and "
+                "Euler coarse steps", i);
+      return FM_ERR_UNSUPPORTED;
     }
     if (f->impl.inst[i].kind == FM_FLOW_EXP && p.max_refine != 0) {
       set_error("prm[%d]: the exponential flow has no refinement (max_refine must be 0)", i);

@@ -886,6 +886,16 @@ fm_status Flow::coarse_propagate(double t1, double t0, int steps, int coarse, co
 // ------------------------------------------------------------ parareal
 fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_params* prm, fm_stats* stats,
                       hipStream_t st) {
+  if (prm[0].variant == FM_PARAREAL_MODIFIED) {
+    fm_status worst = FM_OK;
+    for (int i = 0; i < batch; ++i) {
+      const fm_status r = solve_modified(i, X0 ? X0[i] : nullptr, Xout[i], prm, stats, st);
+      if (r < 0 && r != FM_ERR_NONFINITE) return r;
+      if (r < 0 && (worst >= 0 || r < worst)) worst = r;
+      else if (worst == FM_OK && r != FM_OK) worst = r;
+    }
+    return worst;
+  }
   const size_t e = dt_size(dt), ea = acc_size(dt);
   int Nmax = 0;
   for (int i = 0; i < batch; ++i) Nmax = std::max(Nmax, prm[i].N);
@@ -1318,6 +1328,232 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
   FM_HIP(hipStreamSynchronize(st));
   if (worst == FM_ERR_NONFINITE) set_error("an iterate became non-finite (A(t) singular or the flow diverged)");
   return worst;
+}
+
+// -------------------------------------------------- modified parareal
+// Alg. 3 / Alg. 4 (Sec. 3) for problem i of a linear flow.  Layout: the
+// iterates of two consecutive iterations (Ua, Ub), the basis Q and its fine
+// images FQ (FP64, at most `cap` blocks, device pointer tables for the
+// combination kernel), one FP64 work block per candidate, and the operand
+// buffers of one fine propagation per possible new block and of one coarse
+// propagation.  Every step is a grouped GEMM launch or an FP64 stream kernel;
+// the host reads back two norms per basis candidate (accept / drop) and the
+// slice increments once per iteration.
+fm_status Flow::solve_modified(int i, const double* X0, double* Xout, const fm_params* prm, fm_stats* stats,
+                               hipStream_t st) {
+  const fm_params& p = prm[i];
+  const Inst& in = inst[i];
+  const int N = p.N;
+  const int K = std::min(p.max_iter, N);
+  const bool affine = in.kind == FM_FLOW_INV_LINEAR;
+  const size_t np2 = (size_t)in.np * in.np;
+  const int64_t cnt = (int64_t)np2;
+  const size_t e = dt_size(dt), ea = acc_size(dt);
+  const int64_t cap64 = std::min<int64_t>((int64_t)(K + 1) * (N + 1), (int64_t)in.n * in.n);
+  const int cap = (int)std::max<int64_t>(1, cap64);
+  constexpr int NB = 32;  // dot partial blocks
+  constexpr double DROP = 1e-7;  // remainders below: rounding-dominated directions
+  std::vector<double*> Ua(N + 1), Ub(N + 1), Q(cap), FQ(cap);
+  std::vector<void*> fya(N + 1), fyb(N + 1), fp(N + 1), fk(N + 1);
+  double *W = nullptr, *R = nullptr, *GR = nullptr, *F0 = nullptr, *G0 = nullptr, *C = nullptr;
+  double *alpha = nullptr, *nrm = nullptr, *part_d = nullptr, *incs = nullptr;
+  double **qptr = nullptr, **fqptr = nullptr;
+  void *cy0 = nullptr, *cy1 = nullptr, *cp = nullptr;
+  for (int pass = 0; pass < 2; ++pass) {
+    work.measuring = (pass == 0);
+    work.used = 0;
+    for (int n = 0; n <= N; ++n) {
+      Ua[n] = (double*)work.take(np2 * 8);
+      Ub[n] = (double*)work.take(np2 * 8);
+      fya[n] = work.take(np2 * e);
+      fyb[n] = work.take(np2 * e);
+      fp[n] = work.take(np2 * e);
+      fk[n] = work.take(np2 * ea);
+    }
+    for (int j = 0; j < cap; ++j) {
+      Q[j] = (double*)work.take(np2 * 8);
+      FQ[j] = (double*)work.take(np2 * 8);
+    }
+    W = (double*)work.take(np2 * 8);
+    R = (double*)work.take(np2 * 8);
+    GR = (double*)work.take(np2 * 8);
+    F0 = affine ? (double*)work.take(np2 * 8) : nullptr;
+    G0 = affine ? (double*)work.take(np2 * 8) : nullptr;
+    C = affine ? (double*)work.take(np2 * 8) : nullptr;
+    cy0 = work.take(np2 * e);
+    cy1 = work.take(np2 * e);
+    cp = work.take(np2 * e);
+    alpha = (double*)work.take(sizeof(double) * (cap + 2));
+    nrm = (double*)work.take(sizeof(double) * 4);
+    part_d = (double*)work.take(sizeof(double) * (size_t)(cap + 2 * (N + 1)) * NB);
+    incs = (double*)work.take(sizeof(double) * 2 * (N + 1));
+    qptr = (double**)work.take(sizeof(double*) * cap);
+    fqptr = (double**)work.take(sizeof(double*) * cap);
+    if (pass == 0) FM_TRY(work.reserve(work.used));
+  }
+  FM_HIP(hipStreamSynchronize(st));
+  release_graphs();
+  ring.reset();
+  FM_HIP(hipMemcpyAsync(qptr, Q.data(), sizeof(double*) * cap, hipMemcpyHostToDevice, st));
+  FM_HIP(hipMemcpyAsync(fqptr, FQ.data(), sizeof(double*) * cap, hipMemcpyHostToDevice, st));
+  const double H = p.T / N;
+  auto coarse = [&](const double* xin, double* xout) -> fm_status {
+    std::vector<CoarseSlot> cs(1);
+    cs[0] = CoarseSlot{i, xin, xout, cy0, cy1, cp, nullptr, nullptr, nullptr, 0.0, H / p.coarse_steps, 0, nullptr};
+    return run_coarse(cs, p.coarse_steps, st);
+  };
+  // fine images of blocks src[j] into dst[j], all in one grouped propagation
+  auto fine = [&](const std::vector<const double*>& src, const std::vector<double*>& dst) -> fm_status {
+    if (src.empty()) return FM_OK;
+    std::vector<FineSlot> fs;
+    std::vector<PrepItem> prep;
+    for (size_t j = 0; j < src.size(); ++j) {
+      FM_HIP(copy_f64(dst[j], src[j], cnt, st));
+      fs.push_back(FineSlot{i, dst[j], fya[j], fyb[j], fp[j], fk[j], H / p.fine_steps});
+      prep.push_back(PrepItem{dst[j], nullptr, fya[j], cnt, i, 0});
+    }
+    void* d = nullptr;
+    FM_TRY(push(prep.data(), prep.size() * sizeof(PrepItem), &d, st));
+    FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), dt, nullptr, st));
+    return run_fine(fs, p.fine_steps, p.fine_method, st);
+  };
+  // <q_j, x> for j < s into alpha[0..s)
+  auto project = [&](const double* x, int s) -> fm_status {
+    if (s == 0) return FM_OK;
+    std::vector<DotItem> it;
+    for (int j = 0; j < s; ++j) it.push_back(DotItem{Q[j], x, cnt, j, 0, nullptr});
+    void* d = nullptr;
+    FM_TRY(push(it.data(), it.size() * sizeof(DotItem), &d, st));
+    FM_HIP(launch_dots((const DotItem*)d, s, part_d, NB, alpha, st));
+    return FM_OK;
+  };
+  auto lin = [&](int mode, const double* z, double* out1, double* out2, const double* c, double scale,
+                 int s) -> fm_status {
+    LinItem it{(const double* const*)qptr, (const double* const*)fqptr, alpha, z, c, out1, out2, scale, cnt, s, mode};
+    FM_HIP(launch_lincomb(it, st));
+    return FM_OK;
+  };
+  auto norms2 = [&](const double* a, const double* b, double* h2) -> fm_status {  // ||a||^2, ||b||^2 to host
+    DotItem it[2] = {DotItem{a, a, cnt, 0, 0, nullptr}, DotItem{b, b, cnt, 1, 0, nullptr}};
+    void* d = nullptr;
+    FM_TRY(push(it, sizeof it, &d, st));
+    FM_HIP(launch_dots((const DotItem*)d, 2, part_d, NB, nrm, st));
+    FM_HIP(hipMemcpyAsync(h2, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    FM_HIP(hipStreamSynchronize(st));
+    return FM_OK;
+  };
+
+  // ---- U_0 and Step 0 (coarse sweep); Step -1 for the affine flow
+  std::vector<double*>* U = &Ua;
+  std::vector<double*>* V = &Ub;
+  if (X0) FM_HIP(copy_in((*U)[0], in.np, X0, in.n, st));
+  else FM_HIP(set_identity((*U)[0], in.n, in.np, st));
+  FM_HIP(copy_f64((*V)[0], (*U)[0], cnt, st));
+  for (int n = 0; n < N; ++n) FM_TRY(coarse((*U)[n], (*U)[n + 1]));
+  if (affine) {
+    FM_HIP(hipMemsetAsync(W, 0, np2 * 8, st));
+    FM_TRY(fine({W}, {F0}));
+    FM_TRY(coarse(W, G0));
+    FM_TRY(lin(LIN_AXPY, F0, C, nullptr, G0, -1.0, 0));  // C = F(0) - G(0)
+  }
+  int s = 0, k = 0;
+  double inc = NAN;
+  std::vector<double> hist;
+  fm_status status = FM_OK;
+  while (k < K) {
+    // ---- enlarge the basis with U^k_0 .. U^k_N (CGS, applied twice)
+    const int s0 = s;
+    for (int c = 0; c <= N; ++c) {
+      if (s == cap) break;
+      const double* z = (*U)[c];
+      FM_TRY(project(z, s));
+      FM_TRY(lin(LIN_ORTH, z, W, nullptr, nullptr, 0.0, s));
+      FM_TRY(project(W, s));
+      FM_TRY(lin(LIN_ORTH, W, W, nullptr, nullptr, 0.0, s));
+      double h2[2];
+      FM_TRY(norms2(z, W, h2));
+      if (!std::isfinite(h2[0]) || !std::isfinite(h2[1])) {
+        status = FM_ERR_NONFINITE;
+        break;
+      }
+      const double nz = std::sqrt(h2[0]), rw = std::sqrt(h2[1]);
+      if (rw > DROP * nz && rw > 0) {
+        FM_TRY(lin(LIN_SCALE, W, Q[s], nullptr, nullptr, 1.0 / rw, 0));
+        ++s;
+      }
+    }
+    if (status != FM_OK) break;
+    // ---- fine images of the new blocks (in parallel); affine: minus F(0)
+    {
+      std::vector<const double*> src;
+      std::vector<double*> dst;
+      for (int j = s0; j < s; ++j) {
+        src.push_back(Q[j]);
+        dst.push_back(FQ[j]);
+      }
+      FM_TRY(fine(src, dst));
+      if (affine)
+        for (int j = s0; j < s; ++j) FM_TRY(lin(LIN_AXPY, FQ[j], FQ[j], nullptr, F0, -1.0, 0));
+    }
+    // ---- sweep: U^{k+1}_{n+1} = sum alpha FQ [+ F(0) - G(0)] + G(U - sum alpha Q)
+    for (int n = 0; n < N; ++n) {
+      FM_TRY(project((*V)[n], s));
+      FM_TRY(lin(LIN_SWEEP, (*V)[n], R, (*V)[n + 1], C, 0.0, s));
+      FM_TRY(coarse(R, GR));
+      FM_TRY(lin(LIN_AXPY, (*V)[n + 1], (*V)[n + 1], nullptr, GR, 1.0, 0));
+    }
+    // ---- increment of the iteration
+    {
+      std::vector<DotItem> it;
+      for (int n = 1; n <= N; ++n) {
+        it.push_back(DotItem{(*V)[n], (*V)[n], cnt, 2 * (n - 1), 0, (*U)[n]});
+        it.push_back(DotItem{(*V)[n], (*V)[n], cnt, 2 * (n - 1) + 1, 0, nullptr});
+      }
+      void* d = nullptr;
+      FM_TRY(push(it.data(), it.size() * sizeof(DotItem), &d, st));
+      FM_HIP(launch_dots((const DotItem*)d, (int)it.size(), part_d, NB, incs, st));
+      std::vector<double> h(2 * N);
+      FM_HIP(hipMemcpyAsync(h.data(), incs, 2 * N * sizeof(double), hipMemcpyDeviceToHost, st));
+      FM_HIP(hipStreamSynchronize(st));
+      inc = 0.0;
+      bool finite = true;
+      for (int n = 0; n < N; ++n) {
+        finite &= std::isfinite(h[2 * n]) && std::isfinite(h[2 * n + 1]);
+        const double d2 = std::sqrt(h[2 * n]), s2 = std::sqrt(h[2 * n + 1]);
+        inc = std::max(inc, s2 > 0 ? d2 / s2 : d2);
+      }
+      if (!finite) {
+        status = FM_ERR_NONFINITE;
+        break;
+      }
+    }
+    std::swap(U, V);
+    ring.reset();  // all pushed lists were consumed (the last host read synchronised)
+    ++k;
+    hist.push_back(inc);
+    if (verbose) fprintf(stderr, "[fm] modified parareal problem %d iteration %d: basis %d, increment %.3e\n", i, k, s, inc);
+    if (inc <= p.tol) break;
+  }
+  if (status == FM_OK && k == K && K < N && !(inc <= p.tol)) status = FM_WARN_NOT_CONVERGED;
+  if (stats) {
+    fm_stats& o = stats[i];
+    memset(&o, 0, sizeof o);
+    o.iters = k;
+    o.increment = inc;
+    for (size_t j = 0; j < hist.size() && j < 64; ++j) o.hist[j] = hist[j];
+    o.residual_before = o.residual = NAN;
+    o.basis_size = s;
+  }
+  std::vector<double*> X(batch, nullptr);
+  X[i] = (*U)[N];
+  if (status != FM_ERR_NONFINITE) {
+    if (in.kind != FM_FLOW_EXP) FM_TRY(refine({i}, X, prm, stats, st));
+    FM_HIP(copy_out(Xout, in.n, X[i], in.np, st));
+  }
+  if (stats) stats[i].status = status;
+  FM_HIP(hipStreamSynchronize(st));
+  if (status == FM_ERR_NONFINITE) set_error("an iterate became non-finite");
+  return status;
 }
 
 // ------------------------------------------------- accelerated marching

@@ -271,6 +271,29 @@ __global__ void k_cg_step2(const CgItem* __restrict__ items, const double* __res
     it.p[e] = it.r[e] + b * it.p[e];
 }
 
+
+__global__ void k_lincomb(LinItem it) {
+  for (int64_t e = blockIdx.x * (int64_t)EW_THREADS + threadIdx.x; e < it.count; e += (int64_t)gridDim.x * EW_THREADS) {
+    if (it.mode == LIN_SCALE) {
+      it.out1[e] = it.scale * it.z[e];
+      continue;
+    }
+    if (it.mode == LIN_AXPY) {
+      it.out1[e] = it.z[e] + it.scale * it.c[e];
+      continue;
+    }
+    double p = 0.0, f = 0.0;
+    for (int j = 0; j < it.s; ++j) {
+      const double a = it.alpha[j];
+      p += a * it.q[j][e];
+      if (it.mode == LIN_SWEEP) f += a * it.fq[j][e];
+    }
+    const double z = it.z[e];
+    it.out1[e] = z - p;
+    if (it.mode == LIN_SWEEP) it.out2[e] = it.c ? f + it.c[e] : f;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_dots(const DotItem* items, int nitems, double* part, int nblk, double* out, hipStream_t st) {
@@ -405,6 +428,12 @@ hipError_t launch_dot(const double* a, const double* b, int64_t count, double* p
 hipError_t launch_axpy_dev(double* y, const double* x, const double* alpha_d, double sign, int64_t count,
                            hipStream_t st) {
   hipLaunchKernelGGL(k_axpy_dev, dim3(ew_grid(count)), dim3(EW_THREADS), 0, st, y, x, alpha_d, sign, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb(const LinItem& it, hipStream_t st) {
+  if (it.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lincomb, dim3(ew_grid(it.count)), dim3(EW_THREADS), 0, st, it);
   return hipGetLastError();
 }
 

@@ -156,6 +156,30 @@ struct DotItem {
 };
 hipError_t launch_dots(const DotItem* items, int nitems, double* part, int nblk, double* out, hipStream_t st);
 
+// Linear combinations over a basis of FP64 matrices (the projection and
+// the fine images of the modified parareal, Sec. 3):
+//   LIN_ORTH:  out1 = z - sum_j alpha_j q_j
+//   LIN_SWEEP: out1 = z - sum_j alpha_j q_j,  out2 = sum_j alpha_j fq_j (+ c)
+//   LIN_SCALE: out1 = scale * z
+//   LIN_AXPY:  out1 = z + scale * c
+// q, fq: device arrays of s device pointers; alpha: device, s values; the
+// sum runs over j in order (deterministic).  out1 may alias z.
+enum LinMode { LIN_ORTH = 0, LIN_SWEEP = 1, LIN_SCALE = 2, LIN_AXPY = 3 };
+struct LinItem {
+  const double* const* q;
+  const double* const* fq;
+  const double* alpha;
+  const double* z;
+  const double* c;
+  double* out1;
+  double* out2;
+  double scale;
+  int64_t count;
+  int s;
+  int mode;
+};
+hipError_t launch_lincomb(const LinItem& it, hipStream_t st);
+
 // Conjugate-gradient vector updates for a batch of problems (slot = problem):
 //   step1: alpha = rr[slot] / pap[slot]; h += alpha p; r -= alpha ap
 //   step2: beta = rr_new[slot] / rr[slot]; p = r + beta p

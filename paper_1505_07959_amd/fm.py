@@ -29,6 +29,7 @@ FM_FLOW_INV_LINEAR = 5
 FM_F64, FM_F32, FM_BF16, FM_F16, FM_BF16X3 = 0, 1, 2, 3, 4
 FM_COARSE_EULER, FM_COARSE_LEARNED = 0, 1
 FM_FINE_RK4, FM_FINE_EULER = 0, 1
+FM_PARAREAL_CLASSICAL, FM_PARAREAL_MODIFIED = 0, 1
 
 DTYPES = {"f64": FM_F64, "f32": FM_F32, "bf16": FM_BF16, "f16": FM_F16, "bf16x3": FM_BF16X3}
 
@@ -48,7 +49,7 @@ class fm_params(ctypes.Structure):
     _fields_ = [("T", ctypes.c_double), ("N", ctypes.c_int32), ("coarse_steps", ctypes.c_int32),
                 ("fine_steps", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("coarse", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("tol", ctypes.c_double), ("refine_tol", ctypes.c_double),
-                ("fine_method", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fine_method", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
 class fm_stats(ctypes.Structure):
@@ -56,14 +57,16 @@ class fm_stats(ctypes.Structure):
                 ("status", ctypes.c_int32), ("increment", ctypes.c_double), ("residual_before", ctypes.c_double),
                 ("residual", ctypes.c_double), ("hist", ctypes.c_double * 64),
                 ("fine_launches", ctypes.c_int32), ("learned_restarts", ctypes.c_int32), ("fine_ms", ctypes.c_double),
-                ("fine_flops", ctypes.c_double), ("fine_phase_ms", ctypes.c_double)]
+                ("fine_flops", ctypes.c_double), ("fine_phase_ms", ctypes.c_double),
+                ("basis_size", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {"iters": self.iters, "refine_steps": self.refine_steps, "learned_slices": self.learned_slices,
                 "status": self.status, "increment": self.increment, "residual_before": self.residual_before,
                 "residual": self.residual, "hist": list(self.hist[:max(0, min(self.iters, 64))]),
-                "fine_launches": self.fine_launches, "learned_restarts": self.learned_restarts, "fine_ms": self.fine_ms, "fine_flops": self.fine_flops,
-                "fine_phase_ms": self.fine_phase_ms}
+                "fine_launches": self.fine_launches, "learned_restarts": self.learned_restarts,
+                "fine_ms": self.fine_ms, "fine_flops": self.fine_flops, "fine_phase_ms": self.fine_phase_ms,
+                "basis_size": self.basis_size}
 
 
 def _load():
@@ -156,7 +159,7 @@ def fm_parareal_solve(flow, X0, X_out, params, stream=None):
         prm[i] = fm_params(float(p["T"]), int(p["N"]), int(p.get("coarse_steps", 1)), int(p["fine_steps"]),
                            int(p.get("max_iter", p["N"])), int(p.get("coarse", FM_COARSE_EULER)),
                            int(p.get("max_refine", 0)), float(p.get("tol", 0.0)), float(p.get("refine_tol", 0.0)),
-                           int(p.get("fine_method", FM_FINE_RK4)), 0)
+                           int(p.get("fine_method", FM_FINE_RK4)), int(p.get("variant", FM_PARAREAL_CLASSICAL)))
     stats = (fm_stats * n)()
     x0 = _ptrs(X0)
     st = _check(lib.fm_parareal_solve(flow, x0, _ptrs(X_out), prm, stats, _stream(stream)))

@@ -45,3 +45,41 @@ def test_library_loads_and_resolves():
         assert getattr(lib, name) is not None
     lib.fm_last_error.restype = ctypes.c_char_p
     assert lib.fm_last_error() == b""
+
+
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of fm_problem, fm_params and fm_stats have the sizes
+    and field offsets the C compiler gives the header's structs."""
+    import ctypes
+    import shutil
+    import subprocess
+    import ast
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    fields = {"fm_params": ["T", "N", "fine_steps", "tol", "refine_tol", "fine_method", "variant"],
+              "fm_stats": ["iters", "increment", "hist", "fine_launches", "fine_phase_ms", "basis_size"],
+              "fm_problem": ["kind", "n", "A", "lda"]}
+    prog = ["#include <stdio.h>", "#include <stddef.h>", '#include "fm.h"', "int main(void) {"]
+    for st, fs in fields.items():
+        prog.append('printf("%%zu\\n", sizeof(%s));' % st)
+        for f in fs:
+            prog.append('printf("%%zu\\n", offsetof(%s, %s));' % (st, f))
+    prog.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(prog))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I" + os.path.join(root, "include"), str(c), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    src = open(os.path.join(root, "paper_1505_07959_amd", "fm.py")).read()
+    tree = ast.parse(src)
+    ns = {}
+    body = [n for n in tree.body if isinstance(n, ast.ClassDef) and n.name in fields]
+    exec(compile(ast.Module(body=body, type_ignores=[]), "fm_structs", "exec"), {"ctypes": ctypes}, ns)
+    want = []
+    for st, fs in fields.items():
+        cls = ns[st]
+        want.append(ctypes.sizeof(cls))
+        for f in fs:
+            want.append(getattr(cls, f).offset)
+    assert got == want

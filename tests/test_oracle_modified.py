@@ -94,3 +94,21 @@ def test_faster_than_classical():
     md = modified.modified_parareal(F, G, X0, 10, 10, tol, _fro, _inner)
     assert md["iters"] < cl["iters"]
     assert max(_fro(u - s) / _fro(s) for u, s in zip(md["U"], serial)) < 1e-9
+
+
+def test_global_qr_stays_orthonormal_on_krylov_blocks():
+    """Nearly dependent blocks (a Krylov-like sequence (I + hA)^j X0, the
+    coarse iterates of Step 0): the basis is F-orthonormal to rounding and
+    every block is reproduced, as the proposition after Alg. 2 states."""
+    n = 24
+    A = inputs.nonsymmetric(n, 61, shift=0.5, spread=0.5)
+    X = inputs.perturbed_identity(n, 62, eps=0.3)
+    Z = [X]
+    for _ in range(8):
+        Z.append(Z[-1] + 0.125 * A @ Z[-1])
+    Q, R, kept = modified.global_qr(Z, _inner, _fro)
+    D = modified.diamond(Q, Q, _inner)
+    assert np.abs(D - np.eye(len(Q))).max() < 1e-14
+    for i, z in enumerate(Z):
+        rec = sum(R[j, i] * Q[j] for j in range(len(Q)))
+        assert _fro(z - rec) <= 1e-7 * _fro(z) * 10
