@@ -230,6 +230,21 @@ fm_status fm_coarse_propagate(fm_flow f, double t_next, double t_cur, int32_t st
 fm_status fm_aima(fm_flow f, const double* const* X0, const double* const* E, double dt, int32_t steps,
                   int32_t accel_steps, int32_t every, double* const* X_out, double* hist, void* hip_stream);
 
+/* Sec. 3, Alg. 5: cos(A) for a device n x n FP64 matrix A (row-major,
+ * leading dimension lda), 1 <= n <= 8192.  m = the smallest m >= 0 with
+ * 2^-m ||A||_inf <= 1 and A0 = 2^-m A; cos(A0) is the leading n x n block of
+ * exp(M), M = [[0, -A0], [A0, 0]] (the sine/cosine system of Example 3 with
+ * X0 = 0 in real form), computed as the FM_FLOW_EXP flow of order 2n by
+ * fm_parareal_solve with *prm (T must be 1, max_refine 0; variant, grids
+ * and schemes as given; products in `dtype`); then cos(2X) = 2 cos(X)^2 - I
+ * is applied m times in FP64.  C_out: device n x n, leading dimension n.
+ * m_out (host, may be NULL) receives m; stats (host, may be NULL) those of
+ * the parareal solve.  Allocates its workspace (2n x 2n matrices) per call;
+ * blocks until done.  Returns the solve's status (FM_WARN_NOT_CONVERGED
+ * included) or an error. */
+fm_status fm_cos(const double* A, int64_t n, int64_t lda, int32_t dtype, const fm_params* prm, double* C_out,
+                 int32_t* m_out, fm_stats* stats, const char* options, void* hip_stream);
+
 void fm_destroy(fm_flow f);
 
 /* Thread-local message of the last error (empty string if none). */

@@ -184,6 +184,85 @@ fm_status fm_aima(fm_flow f, const double* const* X0, const double* const* E, do
   return f->impl.aima(X0, E, dt, steps, accel_steps, every, X_out, hist, (hipStream_t)hip_stream);
 }
 
+fm_status fm_cos(const double* A, int64_t n, int64_t lda, int32_t dtype, const fm_params* prm, double* C_out,
+                 int32_t* m_out, fm_stats* stats, const char* options, void* hip_stream) {
+  fm::clear_error();
+  if (!A || !C_out || !prm || n < 1 || n > 8192 || lda < n) {
+    set_error("fm_cos: need A, C_out, prm non-NULL, 1 <= n <= 8192, lda >= n");
+    return FM_ERR_INVALID;
+  }
+  if (prm->T != 1.0 || prm->max_refine != 0) {
+    set_error("fm_cos: prm.T must be 1 and prm.max_refine 0");
+    return FM_ERR_INVALID;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  // ||A||_inf on the device, m = smallest m >= 0 with 2^-m ||A||_inf <= 1
+  double *d_norm = nullptr, *Mb = nullptr, *X = nullptr;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(st);
+    if (d_norm) (void)hipFree(d_norm);
+    if (Mb) (void)hipFree(Mb);
+    if (X) (void)hipFree(X);
+  };
+  const size_t m2 = (size_t)(2 * n) * (size_t)(2 * n);
+  if (hipMalloc((void**)&d_norm, sizeof(double)) != hipSuccess || hipMalloc((void**)&Mb, m2 * 8) != hipSuccess ||
+      hipMalloc((void**)&X, m2 * 8) != hipSuccess) {
+    cleanup();
+    set_error("fm_cos: device allocation failed");
+    return FM_ERR_NOMEM;
+  }
+  double nrm = 0.0;
+  if (fm::launch_norm_inf(A, n, lda, d_norm, st) != hipSuccess ||
+      hipMemcpyAsync(&nrm, d_norm, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess || !std::isfinite(nrm)) {
+    cleanup();
+    set_error("fm_cos: norm of A failed or is not finite");
+    return FM_ERR_DEVICE;
+  }
+  int m = 0;
+  while (std::ldexp(nrm, -m) > 1.0) ++m;
+  if (fm::launch_rotation_generator(Mb, A, n, lda, std::ldexp(1.0, -m), st) != hipSuccess) {
+    cleanup();
+    set_error("fm_cos: kernel launch failed");
+    return FM_ERR_DEVICE;
+  }
+  // exp of the 2n x 2n generator by parareal: its leading block is cos(A0)
+  fm_problem big{FM_FLOW_EXP, 0, 2 * n, Mb, 2 * n};
+  fm_flow fb = nullptr;
+  fm_status s = fm_flow_create(&fb, &big, 1, dtype, options, hip_stream);
+  if (s != FM_OK) {
+    cleanup();
+    return s;
+  }
+  double* xo[1] = {X};
+  fm_status sr = fm_parareal_solve(fb, nullptr, xo, prm, stats, hip_stream);
+  fm_destroy(fb);
+  if (sr < 0) {
+    cleanup();
+    return sr;
+  }
+  if (hipMemcpy2DAsync(C_out, (size_t)n * 8, X, (size_t)(2 * n) * 8, (size_t)n * 8, (size_t)n,
+                       hipMemcpyDeviceToDevice, st) != hipSuccess) {
+    cleanup();
+    set_error("fm_cos: copy of the leading block failed");
+    return FM_ERR_DEVICE;
+  }
+  // cos(2M) = 2 cos(M)^2 - I, m times, in FP64 at order n
+  fm_problem small{FM_FLOW_EXP, 0, n, A, lda};
+  fm_flow fs = nullptr;
+  s = fm_flow_create(&fs, &small, 1, FM_F64, nullptr, hip_stream);
+  if (s != FM_OK) {
+    cleanup();
+    return s;
+  }
+  s = fs->impl.double_angle(C_out, m, st);
+  fm_destroy(fs);
+  cleanup();
+  if (s != FM_OK) return s;
+  if (m_out) *m_out = m;
+  return sr;
+}
+
 void fm_destroy(fm_flow f) {
   if (!f) return;
   int cur = 0;

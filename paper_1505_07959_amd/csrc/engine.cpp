@@ -1330,6 +1330,44 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
   return worst;
 }
 
+// ------------------------------------------------------ double angle
+// Alg. 5 (Sec. 3): C <- 2 C^2 - I, m times, in FP64, for problem 0's order
+// (C: device n x n, leading dimension n, overwritten).  One FP64 product
+// per step with the affine epilogue 2 (C C) - I; operands ping-pong between
+// two zero-padded buffers.
+fm_status Flow::double_angle(double* C, int m, hipStream_t st) {
+  const Inst& in = inst[0];
+  const size_t np2 = (size_t)in.np * in.np;
+  double* P[2] = {nullptr, nullptr};
+  for (int pass = 0; pass < 2; ++pass) {
+    prop.measuring = (pass == 0);
+    prop.used = 0;
+    P[0] = (double*)prop.take(np2 * 8);
+    P[1] = (double*)prop.take(np2 * 8);
+    if (pass == 0) FM_TRY(prop.reserve(prop.used));
+  }
+  FM_HIP(hipStreamSynchronize(st));
+  release_graphs();
+  ring.reset();
+  FM_HIP(copy_in(P[0], in.np, C, in.n, st));
+  for (int j = 0; j < m; ++j) {
+    std::vector<GItem> items(1);
+    std::vector<int> ii(1, 0);
+    GItem& g = items[0];
+    g = blank_item(in, 0);
+    g.a = P[j & 1];
+    g.b = P[j & 1];
+    g.out0 = P[(j & 1) ^ 1];
+    g.s[0] = 2.0;
+    g.s[2] = -1.0;
+    g.flags = F_E_NONE | F_OUT0_F64;
+    FM_TRY(gemm_groups(EPI_AFFINE, items, ii, true, st));
+  }
+  FM_HIP(copy_out(C, in.n, P[m & 1], in.np, st));
+  FM_HIP(hipStreamSynchronize(st));
+  return FM_OK;
+}
+
 // -------------------------------------------------- modified parareal
 // Alg. 3 / Alg. 4 (Sec. 3) for problem i of a linear flow.  Layout: the
 // iterates of two consecutive iterations (Ua, Ub), the basis Q and its fine

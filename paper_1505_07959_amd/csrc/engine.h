@@ -177,6 +177,7 @@ struct Flow {
                            hipStream_t st);
   fm_status coarse_propagate(double t1, double t0, int steps, int coarse, const double* const* xin,
                              double* const* xout, hipStream_t st);
+  fm_status double_angle(double* C, int m, hipStream_t st);
   fm_status solve_modified(int i, const double* X0, double* Xout, const fm_params* prm, fm_stats* stats,
                            hipStream_t st);
   fm_status aima(const double* const* X0, const double* const* E, double dt, int steps, int accel_steps, int every,

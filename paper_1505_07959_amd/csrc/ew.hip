@@ -294,6 +294,40 @@ __global__ void k_lincomb(LinItem it) {
   }
 }
 
+
+// max_i sum_j |a_ij| of an n x n row-major matrix (leading dimension ld), one
+// block; rows are summed in column order, the maximum is order independent.
+__global__ void k_norm_inf(const double* __restrict__ a, int64_t n, int64_t ld, double* __restrict__ out) {
+  __shared__ double sh[EW_THREADS];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += EW_THREADS) {
+    double r = 0.0;
+    for (int64_t j = 0; j < n; ++j) r += fabs(a[i * ld + j]);
+    m = fmax(m, r);
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = EW_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// The real form of the sine/cosine system of Sec. 3, Example 3 (X0 = 0):
+// out = [[0, -c A], [c A, 0]], 2n x 2n row-major (leading dimension 2n).
+__global__ void k_rotation_generator(double* __restrict__ out, const double* __restrict__ a, int64_t n, int64_t ld,
+                                     double c) {
+  const int64_t m = 2 * n, total = m * m;
+  for (int64_t e = blockIdx.x * (int64_t)EW_THREADS + threadIdx.x; e < total; e += (int64_t)gridDim.x * EW_THREADS) {
+    const int64_t i = e / m, j = e % m;
+    double v = 0.0;
+    if (i < n && j >= n) v = -c * a[i * ld + (j - n)];
+    else if (i >= n && j < n) v = c * a[(i - n) * ld + j];
+    out[e] = v;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_dots(const DotItem* items, int nitems, double* part, int nblk, double* out, hipStream_t st) {
@@ -434,6 +468,16 @@ hipError_t launch_axpy_dev(double* y, const double* x, const double* alpha_d, do
 hipError_t launch_lincomb(const LinItem& it, hipStream_t st) {
   if (it.count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_lincomb, dim3(ew_grid(it.count)), dim3(EW_THREADS), 0, st, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_inf(const double* a, int64_t n, int64_t ld, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm_inf, dim3(1), dim3(EW_THREADS), 0, st, a, n, ld, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rotation_generator(double* out, const double* a, int64_t n, int64_t ld, double c, hipStream_t st) {
+  hipLaunchKernelGGL(k_rotation_generator, dim3(ew_grid(4 * n * n)), dim3(EW_THREADS), 0, st, out, a, n, ld, c);
   return hipGetLastError();
 }
 

@@ -180,6 +180,11 @@ struct LinItem {
 };
 hipError_t launch_lincomb(const LinItem& it, hipStream_t st);
 
+// ||A||_inf of an n x n device matrix into out[0] (device).
+hipError_t launch_norm_inf(const double* a, int64_t n, int64_t ld, double* out, hipStream_t st);
+// out (2n x 2n) = [[0, -c A], [c A, 0]].
+hipError_t launch_rotation_generator(double* out, const double* a, int64_t n, int64_t ld, double c, hipStream_t st);
+
 // Conjugate-gradient vector updates for a batch of problems (slot = problem):
 //   step1: alpha = rr[slot] / pap[slot]; h += alpha p; r -= alpha ap
 //   step2: beta = rr_new[slot] / rr[slot]; p = r + beta p

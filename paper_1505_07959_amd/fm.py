@@ -82,6 +82,9 @@ def _load():
     lib.fm_aima.argtypes = [P, PP, PP, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, PP,
                             ctypes.POINTER(ctypes.c_double), P]
     lib.fm_aima.restype = ctypes.c_int
+    lib.fm_cos.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(fm_params), P,
+                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(fm_stats), ctypes.c_char_p, P]
+    lib.fm_cos.restype = ctypes.c_int
     lib.fm_fine_propagate.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, PP, PP, P]
     lib.fm_coarse_propagate.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                         PP, PP, P]
@@ -178,6 +181,25 @@ def fm_aima(flow, X0, E, dt, steps, X_out, accel_steps=None, every=0, stream=Non
     if hist is None:
         return None
     return [list(hist[i * nh:(i + 1) * nh]) for i in range(n)]
+
+
+def fm_cos(A, C_out, params, dtype="f64", options=None, stream=None):
+    """Alg. 5: cos(A) into C_out.  params: dict of fm_params fields (T = 1).
+    Returns (status, m, stats)."""
+    if A.dtype != torch.float64 or not A.is_cuda or not A.is_contiguous():
+        raise FmError(FM_ERR_INVALID, "A must be a contiguous FP64 device tensor")
+    n = A.shape[0]
+    p = params
+    prm = fm_params(float(p.get("T", 1.0)), int(p["N"]), int(p.get("coarse_steps", 1)), int(p["fine_steps"]),
+                    int(p.get("max_iter", p["N"])), int(p.get("coarse", FM_COARSE_EULER)), int(p.get("max_refine", 0)),
+                    float(p.get("tol", 0.0)), float(p.get("refine_tol", 0.0)), int(p.get("fine_method", FM_FINE_RK4)),
+                    int(p.get("variant", FM_PARAREAL_CLASSICAL)))
+    m = ctypes.c_int32(0)
+    stats = fm_stats()
+    st = _check(lib.fm_cos(ctypes.c_void_p(A.data_ptr()), n, n, DTYPES[dtype] if isinstance(dtype, str) else dtype,
+                           ctypes.byref(prm), ctypes.c_void_p(C_out.data_ptr()), ctypes.byref(m),
+                           ctypes.byref(stats), options.encode() if options else None, _stream(stream)))
+    return st, m.value, stats.as_dict()
 
 
 def fm_fine_propagate(flow, t_next, t_cur, steps, X_in, X_out, stream=None):
