@@ -1,0 +1,120 @@
+"""Timing of the paper's own examples and the linear-flow algorithms on one
+GPU (one JSON line per workload).  Inputs are the seeded synthetic matrices
+of ``inputs``; times are wall-clock around the blocking library calls with
+the inputs resident on the device.
+
+    python -m paper_1505_07959_amd.measure_rows [--only NAME ...]
+"""
+
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from paper_1505_07959_amd import fm, inputs
+
+
+def _timed(fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t
+
+
+def _solve(kind, A, prm, dtype="f64", options="timing=1"):
+    n = A.shape[0]
+    h = fm.fm_flow_create([(kind, A)], dtype, options)
+    try:
+        out = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        fm.fm_parareal_solve(h, None, [out], [dict(prm, tol=0.0, max_iter=1)])   # warm-up (autotune, graphs)
+        (st, stats), sec = _timed(lambda: fm.fm_parareal_solve(h, None, [out], [prm]))
+        return stats[0], sec
+    finally:
+        fm.fm_destroy(h)
+
+
+def example1():
+    """Sec. 2, Example 1 at the paper's sizes: n = 80, N = 25, J = 200, Euler."""
+    A = torch.from_numpy(inputs.laplacian_1d(80) / 2 ** 10).cuda()
+    s, sec = _solve(fm.FM_FLOW_INV_HOMOTOPY, A, {"T": 1.0, "N": 25, "fine_steps": 200, "max_iter": 25,
+                                                 "tol": 1e-10, "fine_method": fm.FM_FINE_EULER})
+    return {"workload": "example1_laplacian80_euler_N25_J200", "iterations": s["iters"], "seconds": sec,
+            "note": "latency-bound: 5000 Euler steps of 80 x 80 products per fine sweep"}
+
+
+def exp_variants(n=2048):
+    """exp(T A) by the exponential flow, A = -(SPD, lam in [0.05, 4]), N = 16,
+    16 RK4 steps per slice, FP64, to increment 1e-10: classical vs modified."""
+    A0, Q, lam = inputs.spd(n, "uniform", 0.05, 4.0, 81)
+    A = torch.from_numpy(-A0).cuda()
+    out = []
+    for variant, name in ((fm.FM_PARAREAL_CLASSICAL, "classical"), (fm.FM_PARAREAL_MODIFIED, "modified")):
+        s, sec = _solve(fm.FM_FLOW_EXP, A, {"T": 1.0, "N": 16, "fine_steps": 16, "max_iter": 16, "tol": 1e-10,
+                                            "variant": variant})
+        tf = s["fine_flops"] / (s["fine_ms"] * 1e-3) / 1e12 if s["fine_ms"] > 0 else None
+        out.append({"workload": "exp_flow_n%d_N16_S16_f64_%s" % (n, name), "iterations": s["iters"],
+                    "basis": s["basis_size"], "seconds": sec, "fine_gemm_tflops": tf})
+    return out
+
+
+def aima(m=63, steps=200):
+    """Alg. 8 on the 5-point Laplacian of an m x m grid scaled by its
+    Frobenius norm, dt = 0.1, exact initial error switched off at t = 1:
+    two products per step for the first 10 steps, one after."""
+    L = inputs.laplacian_2d(m)
+    A = L / np.linalg.norm(L)
+    n = A.shape[0]
+    E = torch.from_numpy(np.linalg.inv(A)).cuda()
+    Ad = torch.from_numpy(A).cuda()
+    res = []
+    for dtype in ("f64", "f32"):
+        h = fm.fm_flow_create([(fm.FM_FLOW_INV_LINEAR, Ad)], dtype)
+        try:
+            X = torch.empty((n, n), dtype=torch.float64, device="cuda")
+            fm.fm_aima(h, None, [E], 0.1, 2, [X])
+            _, sec = _timed(lambda: fm.fm_aima(h, None, [E], 0.1, steps, [X], accel_steps=10))
+        finally:
+            fm.fm_destroy(h)
+        acc = min(steps, 10)   # two products per step while the accelerator is on, one after
+        fl = (2 * acc + (steps - acc)) * 2.0 * n ** 3
+        res.append({"workload": "aima_laplacian2d_n%d_%s" % (n, dtype), "steps": steps, "seconds": sec,
+                    "ms_per_step": 1e3 * sec / steps, "tflops": fl / sec / 1e12})
+    return res
+
+
+def cosine(n=2048):
+    """Alg. 5: cos(A), A symmetric with ||A||_inf ~ 8 (m = 3), N = 10, 100
+    RK4 steps per slice on the 2n x 2n system, FP64, tol 1e-12."""
+    A0, Q, lam = inputs.spd(n, "uniform", -4.0, 4.0, 82)
+    A = torch.from_numpy(A0).cuda()
+    C = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    out = []
+    for variant, name in ((fm.FM_PARAREAL_CLASSICAL, "classical"), (fm.FM_PARAREAL_MODIFIED, "modified")):
+        prm = {"N": 10, "fine_steps": 100, "max_iter": 10, "tol": 1e-12, "variant": variant}
+        fm.fm_cos(A, C, dict(prm, max_iter=1, tol=0.0))
+        (st, m, s), sec = _timed(lambda: fm.fm_cos(A, C, prm))
+        ref = (Q * np.cos(lam)) @ Q.T
+        err = float(np.abs(C.cpu().numpy() - ref).max() / np.abs(ref).max())
+        out.append({"workload": "cos_n%d_N10_J100_f64_%s" % (n, name), "m": m, "iterations": s["iters"],
+                    "basis": s["basis_size"], "seconds": sec, "max_rel_error": err})
+    return out
+
+
+ROWS = {"example1": example1, "exp": exp_variants, "aima": aima, "cos": cosine}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--only", nargs="*", default=list(ROWS))
+    a = ap.parse_args()
+    for name in a.only:
+        r = ROWS[name]()
+        for line in (r if isinstance(r, list) else [r]):
+            print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
