@@ -4,9 +4,10 @@
 // parareal stage).
 //
 // Design (CDNA4):
-//  * 256 threads = 4 wavefronts in a 2 x 2 grid; each wave owns a
-//    (BM/2) x (BM/2) block of C built from MFMA tiles (BM = 256 for the
-//    16-bit types: 128 x 128 per wave halves LDS and L2 traffic per flop):
+//  * 256 threads = 4 wavefronts in a 2 x 2 grid, each owning a (BM/2) x
+//    (BM/2) block of C built from MFMA tiles; the 256-wide 16-bit tiles use
+//    512 threads = 8 wavefronts in a 2 x 4 grid (128 x 64 per wave, two
+//    waves per SIMD, half the L2 traffic per flop of the 128-wide tiles):
 //      FP64  v_mfma_f64_16x16x4f64     (16x16 blocks, FP64 accumulate)
 //      FP32  v_mfma_f32_32x32x2f32     (32x32 blocks)
 //      BF16  v_mfma_f32_32x32x16_bf16  (32x32 blocks, FP32 accumulate)
@@ -291,8 +292,15 @@ __device__ __forceinline__ void epilogue4(const GItem& it, int64_t idx, int dpos
   }
 }
 
+// Threads per workgroup: the 256-wide 16-bit tiles use 8 waves (2 x 4, each
+// 128 x 64) so that two waves share every SIMD; the others 4 waves (2 x 2).
+template <int DT, int BM>
+constexpr int gemm_nt() {
+  return (BM == 256 && DT != DT_F64 && DT != DT_F32) ? 512 : 256;
+}
+
 template <int DT, int BM, int BK, int EPI>
-__global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 : 1) void gemm_kernel(const GItem* __restrict__ items,
+__global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 : 1) void gemm_kernel(const GItem* __restrict__ items,
                                                    const int* __restrict__ tile_start, int nitems,
                                                    int total_tiles, const int* __restrict__ live) {
   using TR = Tr<DT>;
@@ -303,7 +311,9 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
   using FV = typename TR::FV;
   constexpr int MI = TR::MI, V = TR::V, NACC = TR::NACC;
   constexpr int BN = BM;
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int NT = gemm_nt<DT, BM>();  // threads
+  constexpr int NWC = NT / 128;          // waves along N (2 along M)
+  constexpr int WM = BM / 2, WN = BN / NWC;
   constexpr int RM = WM / MI, RN = WN / MI;
   constexpr int NQ = 64 / MI;            // lane groups along k
   constexpr int KC = NQ * V;             // k per chunk
@@ -313,10 +323,10 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
   constexpr int A_CHUNKS = BM * BK / W;  // 16-byte chunks of an A tile
   constexpr int B_BLOCKS = (BK / V) * (BN / W);
   static_assert(BK % KC == 0, "BK must be a multiple of the MFMA k chunk");
-  static_assert(A_CHUNKS % 256 == 0, "A tile must split evenly over 256 threads");
-  static_assert(B_BLOCKS <= 256 || B_BLOCKS % 256 == 0, "B tile split");
-  constexpr int A_PER_T = A_CHUNKS / 256;
-  constexpr int B_PER_T = B_BLOCKS >= 256 ? B_BLOCKS / 256 : 1;
+  static_assert(A_CHUNKS % NT == 0, "A tile must split evenly over the threads");
+  static_assert(B_BLOCKS <= NT || B_BLOCKS % NT == 0, "B tile split");
+  constexpr int A_PER_T = A_CHUNKS / NT;
+  constexpr int B_PER_T = B_BLOCKS >= NT ? B_BLOCKS / NT : 1;
   // pipeline step: SUBV k-values per lane (FP64/FP32: half of the lane's
   // 4-vector, 2 MFMAs deep; 16-bit: one MFMA), SUB steps per KC chunk
   constexpr int SUBV = (DT == DT_F64 || DT == DT_F32) ? 2 : V;
@@ -346,7 +356,7 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / NWC, wc = wave % NWC;
   const int lr = lane % MI, lq = lane / MI;
 
   // tile range of this workgroup
@@ -424,14 +434,14 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
           const_cast<T*>(Bs_g), (short)0, ((BK - 1) * np + BN) * (int)sizeof(T), 0x00020000);
 #pragma unroll
       for (int u = 0; u < A_PER_T; ++u) {
-        const int c = tid + 256 * u;
+        const int c = tid + NT * u;
         const int r = c / (BK / W), cc = c % (BK / W);
         ra[set][u] = __builtin_bit_cast(G16, __builtin_amdgcn_raw_buffer_load_b128(
                                             ra_rs, (r * np + cc * W) * (int)sizeof(T), 0, 0));
       }
 #pragma unroll
       for (int u = 0; u < B_PER_T; ++u) {
-        const int blk = tid + 256 * u;
+        const int blk = tid + NT * u;
         b_active[u] = blk < B_BLOCKS;
         if (b_active[u]) {
           const int kb = blk / (BN / W), cb = blk % (BN / W);
@@ -445,14 +455,14 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
     auto lstore = [&](int buf, int set) {
 #pragma unroll
       for (int u = 0; u < A_PER_T; ++u) {
-        const int c = tid + 256 * u;
+        const int c = tid + NT * u;
         const int r = c / (BK / W), cc = c % (BK / W);
         *(G16*)(&As[buf][r * LDA_S + cc * W]) = ra[set][u];
       }
 #pragma unroll
       for (int u = 0; u < B_PER_T; ++u) {
         if (b_active[u]) {
-          const int blk = tid + 256 * u;
+          const int blk = tid + NT * u;
           const int kb = blk / (BN / W), cb = blk % (BN / W);
 #pragma unroll
           for (int w = 0; w < W; ++w) {
@@ -550,7 +560,7 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
     }
 
     // Fused epilogue, staged through LDS in RM passes: in pass i every wave
-    // writes its accumulator row block i (MI rows), then all 256 threads
+    // writes its accumulator row block i (MI rows), then all threads
     // walk the 2*MI x BN staged rows in row-major order, so the epilogue's
     // global traffic is coalesced and the accumulators are only ever
     // indexed statically.
@@ -573,7 +583,7 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
             Cs[(wr * MI + r) * CLD + wc * WN + j * MI + c] = (Acc)acc[i][j][v];
           }
         __syncthreads();
-        for (int e = tid; e < CROWS * BN / EV; e += 256) {
+        for (int e = tid; e < CROWS * BN / EV; e += NT) {
           const int rr = (e * EV) / BN, cc = (e * EV) % BN;
           const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
           const int gc = col0 + cc;
@@ -591,7 +601,7 @@ __global__ __launch_bounds__(256, (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 
 template <int DT, int BM, int BK>
 hipError_t launch_cfg(int epi, const GItem* items, const int* ts, int nitems, int total, int grid,
                       const int* live, hipStream_t st) {
-  dim3 g(grid), b(256);
+  dim3 g(grid), b(gemm_nt<DT, BM>());
   switch (epi) {
     case EPI_AFFINE: hipLaunchKernelGGL((gemm_kernel<DT, BM, BK, EPI_AFFINE>), g, b, 0, st, items, ts, nitems, total, live); break;
     case EPI_RK4: hipLaunchKernelGGL((gemm_kernel<DT, BM, BK, EPI_RK4>), g, b, 0, st, items, ts, nitems, total, live); break;
@@ -606,7 +616,8 @@ hipError_t launch_cfg(int epi, const GItem* items, const int* ts, int nitems, in
 template <int DT, int BM, int BK>
 int occupancy_cfg() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_kernel<DT, BM, BK, EPI_RK4>, 256, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_kernel<DT, BM, BK, EPI_RK4>, gemm_nt<DT, BM>(), 0) !=
+          hipSuccess ||
       nb < 1)
     nb = 1;
   return nb;
