@@ -125,7 +125,7 @@ typedef struct {
   int32_t N;             /* slices, 1..4096 */
   int32_t coarse_steps;  /* >= 1 */
   int32_t fine_steps;    /* >= 1 */
-  int32_t max_iter;      /* >= 0 (0: coarse sweep only) */
+  int32_t max_iter;      /* >= 0 (0: the coarse sweep only, status FM_OK) */
   int32_t coarse;        /* fm_coarse */
   int32_t max_refine;    /* >= 0 */
   double tol;            /* >= 0 */

@@ -1572,7 +1572,7 @@ fm_status Flow::solve_modified(int i, const double* X0, double* Xout, const fm_p
     if (verbose) fprintf(stderr, "[fm] modified parareal problem %d iteration %d: basis %d, increment %.3e\n", i, k, s, inc);
     if (inc <= p.tol) break;
   }
-  if (status == FM_OK && k == K && K < N && !(inc <= p.tol)) status = FM_WARN_NOT_CONVERGED;
+  if (status == FM_OK && K > 0 && k == K && K < N && !(inc <= p.tol)) status = FM_WARN_NOT_CONVERGED;
   if (stats) {
     fm_stats& o = stats[i];
     memset(&o, 0, sizeof o);

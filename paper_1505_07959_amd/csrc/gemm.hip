@@ -327,6 +327,14 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
   static_assert(B_BLOCKS <= NT || B_BLOCKS % NT == 0, "B tile split");
   constexpr int A_PER_T = A_CHUNKS / NT;
   constexpr int B_PER_T = B_BLOCKS >= NT ? B_BLOCKS / NT : 1;
+  // When the tile has fewer B blocks (V rows x 16 bytes) than threads, the
+  // RSPLIT threads of a block share its rows (VR each) so that every thread
+  // loads and stores the same amount; their LDS stores are VR-element parts
+  // of the k-vectors.
+  constexpr int RSPLIT = B_BLOCKS < NT ? NT / B_BLOCKS : 1;
+  constexpr int VR = V / RSPLIT;
+  static_assert(V % RSPLIT == 0 && B_BLOCKS * RSPLIT >= NT, "B row split");
+  typedef T PV __attribute__((ext_vector_type(VR)));
   // pipeline step: SUBV k-values per lane (FP64/FP32: half of the lane's
   // 4-vector, 2 MFMAs deep; 16-bit: one MFMA), SUB steps per KC chunk
   constexpr int SUBV = (DT == DT_F64 || DT == DT_F32) ? 2 : V;
@@ -413,8 +421,7 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
 
     // PF register staging sets: tile kt's global loads land in set kt % PF
     G16 ra[PF][A_PER_T];
-    G16 rb[PF][B_PER_T][V];
-    bool b_active[B_PER_T];
+    G16 rb[PF][B_PER_T][VR];
 
     const int64_t np2 = (int64_t)np * np;
     const int nkps = np / BK;  // K tiles per segment
@@ -441,15 +448,13 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
       }
 #pragma unroll
       for (int u = 0; u < B_PER_T; ++u) {
-        const int blk = tid + NT * u;
-        b_active[u] = blk < B_BLOCKS;
-        if (b_active[u]) {
-          const int kb = blk / (BN / W), cb = blk % (BN / W);
+        const int blk = RSPLIT > 1 ? tid % B_BLOCKS : tid + NT * u;
+        const int r0 = RSPLIT > 1 ? (tid / B_BLOCKS) * VR : 0;
+        const int kb = blk / (BN / W), cb = blk % (BN / W);
 #pragma unroll
-          for (int r = 0; r < V; ++r)
-            rb[set][u][r] = __builtin_bit_cast(G16, __builtin_amdgcn_raw_buffer_load_b128(
-                                                   rb_rs, ((kb * V + r) * np + cb * W) * (int)sizeof(T), 0, 0));
-        }
+        for (int r = 0; r < VR; ++r)
+          rb[set][u][r] = __builtin_bit_cast(G16, __builtin_amdgcn_raw_buffer_load_b128(
+                                                 rb_rs, ((kb * V + r0 + r) * np + cb * W) * (int)sizeof(T), 0, 0));
       }
     };
     auto lstore = [&](int buf, int set) {
@@ -459,18 +464,25 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
         const int r = c / (BK / W), cc = c % (BK / W);
         *(G16*)(&As[buf][r * LDA_S + cc * W]) = ra[set][u];
       }
+      // The B store addresses are recomputed at every store from an opaque
+      // copy of the thread index: hoisted out of the K loop they would hold
+      // W registers per thread for the whole loop.
+      int tid_o = tid;
+      asm volatile("" : "+v"(tid_o));
 #pragma unroll
       for (int u = 0; u < B_PER_T; ++u) {
-        if (b_active[u]) {
-          const int blk = tid + NT * u;
-          const int kb = blk / (BN / W), cb = blk % (BN / W);
+        const int blk = RSPLIT > 1 ? tid_o % B_BLOCKS : tid_o + NT * u;
+        const int r0 = RSPLIT > 1 ? (tid_o / B_BLOCKS) * VR : 0;
+        const int kb = blk / (BN / W), cb = blk % (BN / W);
+        T* bcol = &Bs[buf][(kb * BN + cb * W) * V + r0];
+        const int sw = cb & (GS - 1);
 #pragma unroll
-          for (int w = 0; w < W; ++w) {
-            LV col;
+        for (int w = 0; w < W; ++w) {
+          PV col;
 #pragma unroll
-            for (int r = 0; r < V; ++r) col[r] = rb[set][u][r][w];
-            *(LV*)(&Bs[buf][(kb * BN + bswz(cb * W + w)) * V]) = col;
-          }
+          for (int r = 0; r < VR; ++r) col[r] = rb[set][u][r][w];
+          // bswz(cb * W + w) = cb * W + (w ^ (cb & (GS - 1))) for W == GS
+          *(PV*)(bcol + ((W == GS ? (w ^ sw) : (bswz(cb * W + w) - cb * W)) * V)) = col;
         }
       }
     };

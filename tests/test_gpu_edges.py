@@ -1,0 +1,92 @@
+"""Edge cases of the parareal driver on the GPU against the oracle: the
+smallest orders (1 x 1 and one element past a 64-wide tile), one slice, zero
+iterations, an immediately satisfied tolerance, more iterations requested
+than slices, a start value given by the caller, and a homotopy whose path
+A(t) becomes singular (the library must report FM_ERR_NONFINITE)."""
+
+import numpy as np
+import pytest
+
+from oracle import MatrixAlgebra, HOMOTOPY, STEADY_INV, integrators, parareal
+from paper_1505_07959_amd import inputs
+from tests.gpu_util import dev, host, empty, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(kind, A, X0, T, N, S, K, tol):
+    alg = MatrixAlgebra(A.shape[0])
+    t = [i * T / N for i in range(N + 1)]
+    F = lambda i, x: integrators.fine(alg, kind, A, x, t[i + 1], t[i], S)
+    G = lambda i, x: integrators.coarse(alg, kind, A, x, t[i + 1], t[i], 1)
+    return parareal.parareal(F, G, X0, N, K, tol, alg.fro)
+
+
+def _solve(kind, A, prm, X0=None):
+    from paper_1505_07959_amd import fm
+    n = A.shape[0]
+    h = fm.fm_flow_create([(kind, dev(A))], "f64")
+    try:
+        out = empty(n)
+        st, stats = fm.fm_parareal_solve(h, None if X0 is None else [dev(X0)], [out], [prm])
+        return st, stats[0], host(out)
+    finally:
+        fm.fm_destroy(h)
+
+
+@pytest.mark.parametrize("n", [1, 2, 65])
+def test_smallest_and_ragged_orders(n):
+    A, Q, lam = inputs.spd(n, "uniform", 0.3, 2.0, 90 + n)
+    ref = _oracle(HOMOTOPY, A, np.eye(n), 1.0, 6, 8, 3, 0.0)
+    st, s, X = _solve(HOMOTOPY, A, {"T": 1.0, "N": 6, "fine_steps": 8, "max_iter": 3, "tol": 0.0})
+    e = rel(X, ref["U"][-1])
+    say("  n=%d: iters %d, vs oracle %.2e" % (n, s["iters"], e))
+    assert s["iters"] == 3 and e <= 1e-12
+
+
+def test_one_slice_zero_iterations_and_caps():
+    from paper_1505_07959_amd import fm
+    n = 40
+    A, Q, lam = inputs.spd(n, "uniform", 0.3, 2.0, 95)
+    # N = 1: one iteration is the fine solution itself (k = N)
+    ref = _oracle(HOMOTOPY, A, np.eye(n), 1.0, 1, 16, 5, 0.0)
+    st, s, X = _solve(HOMOTOPY, A, {"T": 1.0, "N": 1, "fine_steps": 16, "max_iter": 5, "tol": 0.0})
+    assert s["iters"] == ref["iters"] == 1 and rel(X, ref["U"][-1]) <= 1e-13
+    # max_iter = 0: the coarse sweep only (an explicit request: status OK)
+    ref = _oracle(HOMOTOPY, A, np.eye(n), 1.0, 4, 8, 0, 0.0)
+    st, s, X = _solve(HOMOTOPY, A, {"T": 1.0, "N": 4, "fine_steps": 8, "max_iter": 0, "tol": 0.0})
+    assert s["iters"] == 0 and rel(X, ref["U"][-1]) <= 1e-13 and st == fm.FM_OK
+    # stopping at max_iter short of the tolerance is reported
+    st, s, X = _solve(HOMOTOPY, A, {"T": 1.0, "N": 4, "fine_steps": 8, "max_iter": 1, "tol": 1e-30})
+    assert s["iters"] == 1 and st == fm.FM_WARN_NOT_CONVERGED
+    # more iterations than slices: capped at k = N (exact termination)
+    ref = _oracle(HOMOTOPY, A, np.eye(n), 1.0, 3, 8, 10, 0.0)
+    st, s, X = _solve(HOMOTOPY, A, {"T": 1.0, "N": 3, "fine_steps": 8, "max_iter": 10, "tol": 0.0})
+    assert s["iters"] == ref["iters"] == 3 and rel(X, ref["U"][-1]) <= 1e-13 and st == fm.FM_OK
+    # a huge tolerance stops after the first iteration
+    st, s, X = _solve(HOMOTOPY, A, {"T": 1.0, "N": 4, "fine_steps": 8, "max_iter": 4, "tol": 1e3})
+    assert s["iters"] == 1 and st == fm.FM_OK
+
+
+def test_caller_start_value_steady_flow():
+    n = 48
+    A, Q, lam = inputs.spd(n, "uniform", 0.5, 1.5, 96)
+    X0 = 0.7 * inputs.perturbed_identity(n, 97, eps=0.2)
+    ref = _oracle(STEADY_INV, A, X0, 6.0, 6, 8, 2, 0.0)
+    st, s, X = _solve(STEADY_INV, A, {"T": 6.0, "N": 6, "fine_steps": 8, "max_iter": 2, "tol": 0.0}, X0)
+    assert rel(X, ref["U"][-1]) <= 1e-12
+
+
+def test_singular_homotopy_path_is_reported():
+    """An eigenvalue -500 makes A(t) = I + t(A - I) singular at t = 1/501:
+    the Euler coarse sweep overflows (x_{j+1} = x_j + dT 501 x_j^2 reaches
+    inf by the eighth slice) and the solve returns FM_ERR_NONFINITE."""
+    from paper_1505_07959_amd import fm
+    n = 16
+    A, Q, lam = inputs.spd(n, "uniform", 0.5, 2.0, 98)
+    lam = lam.copy()
+    lam[0] = -500.0
+    A = (Q * lam) @ Q.T
+    with pytest.raises(fm.FmError) as ei:
+        _solve(HOMOTOPY, A, {"T": 1.0, "N": 8, "fine_steps": 16, "max_iter": 8, "tol": 0.0})
+    assert ei.value.status == fm.FM_ERR_NONFINITE
