@@ -198,7 +198,8 @@ __device__ __forceinline__ void st_op4(void* p, int64_t idx, int64_t np2, const 
   }
 }
 
-// Fused epilogue for the four elements (gr, gc .. gc+3) of item `it`
+// Single-pass fused epilogue (the FP64/FP32 products) for the four elements
+// (gr, gc .. gc+3) of item `it`
 // (idx = gr*np + gc); element `dpos` (or none, -1) lies on the leading
 // n x n diagonal.  Per element the arithmetic is that of the propagator
 // step being fused: a = (A B)[gr, gc] in the accumulation precision.
@@ -284,6 +285,120 @@ __device__ __forceinline__ void epilogue4(const GItem& it, int64_t idx, int dpos
     V4 v;
 #pragma unroll
     for (int e = 0; e < EV; ++e) v.v[e] = a.v[e] + s[5] * p0.v[e] + s[6] * p1.v[e] + s[7] * p2.v[e];
+#pragma unroll
+    for (int e = 0; e < EV; ++e)
+      if (e == dpos) v.v[e] += s[4];
+    gst4<double>(it.out1, idx, v);
+    st_op4<DT>(it.out0, idx, np2, v);
+  }
+}
+
+// The same epilogue split in two phases, used for the 16-bit products
+// whose epilogue is bound by memory latency: a thread issues the global
+// loads of several element groups (epi_load) before it combines any of them
+// with the products and stores (epi_apply).
+struct EpiIn {
+  V4 p, q, r;  // RK4/Euler: state, stage accumulator, E; POLYP/POLYX: in0, in1, in2 (E in r for AFFINE)
+};
+
+template <int DT, int EPI>
+__device__ __forceinline__ EpiIn epi_load(const GItem& it, int64_t idx) {
+  using Acc = typename Tr<DT>::Acc;
+  const int64_t np2 = (int64_t)it.np * it.np;
+  EpiIn in;
+  auto load_e = [&]() -> V4 {
+    return (it.flags & F_E_F64) ? gld4<double>(it.in0, idx) : ld_op4<DT>(it.in0, idx, np2);
+  };
+  if constexpr (EPI == EPI_AFFINE) {
+    if (!(it.flags & F_E_NONE)) in.r = load_e();
+  } else if constexpr (EPI == EPI_RK4 || EPI == EPI_EULER) {
+    if (!(it.flags & F_E_NONE)) in.r = load_e();
+    in.p = gld4<double>(it.x, idx);
+    if constexpr (EPI == EPI_RK4)
+      if (it.stage >= 2) in.q = gld4<Acc>(it.out1, idx);
+  } else if constexpr (EPI == EPI_POLYP) {
+    in.p = ld_op4<DT>(it.in0, idx, np2);
+    in.q = ld_op4<DT>(it.in1, idx, np2);
+  } else {
+    in.p = ld_op4<DT>(it.in0, idx, np2);
+    in.q = ld_op4<DT>(it.in1, idx, np2);
+    in.r = ld_op4<DT>(it.in2, idx, np2);
+  }
+  return in;
+}
+
+template <int DT, int EPI>
+__device__ __forceinline__ void epi_apply(const GItem& it, int64_t idx, int dpos, const V4& a, const EpiIn& in) {
+  using Acc = typename Tr<DT>::Acc;
+  const double* s = it.s;
+  const int64_t np2 = (int64_t)it.np * it.np;
+  if constexpr (EPI == EPI_AFFINE) {
+    V4 v;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) v.v[e] = s[0] * a.v[e];
+    if (!(it.flags & F_E_NONE)) {
+#pragma unroll
+      for (int e = 0; e < EV; ++e) v.v[e] += s[1] * in.r.v[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EV; ++e)
+      if (e == dpos) v.v[e] += s[2];
+    if (it.flags & F_OUT0_F64) gst4<double>(it.out0, idx, v);
+    else st_op4<DT>(it.out0, idx, np2, v);
+  } else if constexpr (EPI == EPI_RK4 || EPI == EPI_EULER) {
+    V4 k;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) k.v[e] = s[0] * a.v[e];
+    if (!(it.flags & F_E_NONE)) {
+#pragma unroll
+      for (int e = 0; e < EV; ++e) k.v[e] += s[1] * in.r.v[e];
+    }
+    if (s[3] != 0.0) {  // identity term of the field (dX/dt = I - A X)
+#pragma unroll
+      for (int e = 0; e < EV; ++e)
+        if (e == dpos) k.v[e] += s[3];
+    }
+    const double h = s[2];
+    const V4& x = in.p;
+    V4 o;
+    if constexpr (EPI == EPI_EULER) {
+#pragma unroll
+      for (int e = 0; e < EV; ++e) o.v[e] = x.v[e] + h * k.v[e];
+      gst4<double>(it.out1, idx, o);
+    } else {
+      void* K = it.out1;
+      if (it.stage == 1) {
+        gst4<Acc>(K, idx, k);
+#pragma unroll
+        for (int e = 0; e < EV; ++e) o.v[e] = x.v[e] + 0.5 * h * k.v[e];
+      } else if (it.stage == 2 || it.stage == 3) {
+        V4 kk = in.q;
+#pragma unroll
+        for (int e = 0; e < EV; ++e) kk.v[e] = kk.v[e] + 2.0 * k.v[e];
+        gst4<Acc>(K, idx, kk);
+        const double c = it.stage == 2 ? 0.5 * h : h;
+#pragma unroll
+        for (int e = 0; e < EV; ++e) o.v[e] = x.v[e] + c * k.v[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < EV; ++e) o.v[e] = x.v[e] + (h / 6.0) * (in.q.v[e] + k.v[e]);
+        gst4<double>(it.x, idx, o);
+      }
+    }
+    st_op4<DT>(it.out0, idx, np2, o);
+  } else if constexpr (EPI == EPI_POLYP) {
+    V4 v;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) v.v[e] = s[1] * in.p.v[e] + s[2] * in.q.v[e] + s[3] * a.v[e];
+#pragma unroll
+    for (int e = 0; e < EV; ++e)
+      if (e == dpos) v.v[e] += s[0];
+    st_op4<DT>(it.out0, idx, np2, v);
+    st_op4<DT>(it.out1, idx, np2, a);
+  } else {  // EPI_POLYX
+    V4 v;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) v.v[e] = a.v[e] + s[5] * in.p.v[e] + s[6] * in.q.v[e] + s[7] * in.r.v[e];
 #pragma unroll
     for (int e = 0; e < EV; ++e)
       if (e == dpos) v.v[e] += s[4];
@@ -595,15 +710,47 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
             Cs[(wr * MI + r) * CLD + wc * WN + j * MI + c] = (Acc)acc[i][j][v];
           }
         __syncthreads();
-        for (int e = tid; e < CROWS * BN / EV; e += NT) {
-          const int rr = (e * EV) / BN, cc = (e * EV) % BN;
-          const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
-          const int gc = col0 + cc;
-          V4 a;
+        // ITER element groups per thread, handled EG at a time: the loads
+        // of a batch are all issued before its first group is combined
+        constexpr int ITER = CROWS * BN / EV / NT;
+        constexpr int EG = (DT == DT_F64 || DT == DT_F32) ? 1 : (ITER < 2 ? ITER : 2);
+        static_assert(CROWS * BN / EV % NT == 0 && ITER % EG == 0, "epilogue split");
+        if constexpr (EG == 1) {
+          for (int e = tid; e < CROWS * BN / EV; e += NT) {
+            const int rr = (e * EV) / BN, cc = (e * EV) % BN;
+            const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
+            const int gc = col0 + cc;
+            V4 a;
 #pragma unroll
-          for (int q = 0; q < EV; ++q) a.v[q] = (double)Cs[rr * CLD + cc + q];
-          const int dpos = (gr >= gc && gr < gc + EV && gr < n_valid) ? gr - gc : -1;
-          epilogue4<DT, EPI>(it, (int64_t)gr * np + gc, dpos, a);
+            for (int q = 0; q < EV; ++q) a.v[q] = (double)Cs[rr * CLD + cc + q];
+            const int dpos = (gr >= gc && gr < gc + EV && gr < n_valid) ? gr - gc : -1;
+            epilogue4<DT, EPI>(it, (int64_t)gr * np + gc, dpos, a);
+          }
+        } else
+#pragma unroll
+        for (int g0 = 0; g0 < ITER; g0 += EG) {
+          EpiIn in[EG];
+          int64_t idx[EG];
+#pragma unroll
+          for (int g = 0; g < EG; ++g) {
+            const int e = tid + (g0 + g) * NT;
+            const int rr = (e * EV) / BN, cc = (e * EV) % BN;
+            const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
+            idx[g] = (int64_t)gr * np + col0 + cc;
+            in[g] = epi_load<DT, EPI>(it, idx[g]);
+          }
+#pragma unroll
+          for (int g = 0; g < EG; ++g) {
+            const int e = tid + (g0 + g) * NT;
+            const int rr = (e * EV) / BN, cc = (e * EV) % BN;
+            const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
+            const int gc = col0 + cc;
+            V4 a;
+#pragma unroll
+            for (int q = 0; q < EV; ++q) a.v[q] = (double)Cs[rr * CLD + cc + q];
+            const int dpos = (gr >= gc && gr < gc + EV && gr < n_valid) ? gr - gc : -1;
+            epi_apply<DT, EPI>(it, idx[g], dpos, a, in[g]);
+          }
         }
       }
     }
