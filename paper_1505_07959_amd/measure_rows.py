@@ -103,7 +103,62 @@ def cosine(n=2048):
     return out
 
 
-ROWS = {"example1": example1, "exp": exp_variants, "aima": aima, "cos": cosine}
+def batched(count=512, tol=1e-3):
+    """The batched workload: 512 problems, n uniform on {32, ..., 512}, half
+    inverse homotopy (T = 1), half A - X^2 (T = 20), BF16 products, N = 64,
+    8 RK4 steps per slice, to increment 1e-3, then FP64 refinement."""
+    cases = [inputs.batched_instance(i) for i in range(count)]
+    prm = [{"T": T, "N": 64, "fine_steps": 8, "coarse_steps": 1 if k == fm.FM_FLOW_INV_HOMOTOPY else 2,
+            "max_iter": 64, "tol": tol, "max_refine": 6, "refine_tol": 1e-13} for k, T, *_ in cases]
+    flow = fm.fm_flow_create([(k, torch.from_numpy(A).cuda()) for k, T, A, Q, lam in cases], "bf16")
+    try:
+        outs = [torch.empty((c[2].shape[0],) * 2, dtype=torch.float64, device="cuda") for c in cases]
+        fm.fm_parareal_solve(flow, None, outs, [dict(p, max_iter=1, max_refine=0) for p in prm])
+        (st, stats), sec = _timed(lambda: fm.fm_parareal_solve(flow, None, outs, prm))
+    finally:
+        fm.fm_destroy(flow)
+    its = [s["iters"] for s in stats]
+    return {"workload": "batched%d_bf16_N64_S8_tol%g_refined" % (count, tol), "seconds": sec, "solves_per_s": count / sec,
+            "iterations_max": max(its), "iterations_mean": float(np.mean(its)),
+            "refine_steps_max": max(s["refine_steps"] for s in stats),
+            "residual_max": max(s["residual"] for s in stats)}
+
+
+def learned_vs_euler(kind=fm.FM_FLOW_INV_HOMOTOPY):
+    """Learned vs Euler coarse step: the n = 2048 homotopy (N = 128, S = 8,
+    FP64, to 1e-8) or the n = 8192 X - XAX flow (N = 32, S = 16, T = 30,
+    FP16 products, to 1e-3), each after one warm-up solve of the flow."""
+    from paper_1505_07959_amd import eval_coarse
+    if kind == fm.FM_FLOW_INV_HOMOTOPY:
+        n, N, S, T, dt, tol = 2048, 128, 8, 1.0, "f64", 1e-8
+        A = inputs.learned_eval_problem(n)[0]
+    else:
+        n, N, S, T, dt, tol = 8192, 32, 16, 30.0, "f16", 1e-3
+        A = inputs.steady_problem(n)[0]
+    Ad = torch.from_numpy(A).cuda()
+    model = eval_coarse.DEFAULT_MODEL[kind]
+    flow = fm.fm_flow_create([(kind, Ad)], dt, "coarse_model=%s" % model)
+    out = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    res = []
+    try:
+        fm.fm_parareal_solve(flow, None, [out], [{"T": T, "N": N, "fine_steps": S, "max_iter": 1, "tol": 0.0}])
+        for name, coarse in (("euler", fm.FM_COARSE_EULER), ("learned", fm.FM_COARSE_LEARNED)):
+            prm = {"T": T, "N": N, "fine_steps": S, "max_iter": N, "tol": tol, "coarse": coarse}
+            (st, stats), sec = _timed(lambda: fm.fm_parareal_solve(flow, None, [out], [prm]))
+            s = stats[0]
+            res.append({"workload": "%s_n%d_N%d_S%d_%s_tol%g_%s" % ("homotopy" if kind == 1 else "steady", n, N, S,
+                                                                    dt, tol, name),
+                        "iterations": s["iters"], "seconds": sec, "restarts": s["learned_restarts"],
+                        "status": st})
+    finally:
+        fm.fm_destroy(flow)
+    return res
+
+
+ROWS = {"example1": example1, "exp": exp_variants, "aima": aima, "cos": cosine, "batched": batched,
+        "batched_tol1e-2": lambda: batched(tol=1e-2),
+        "learned": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY),
+        "learned_steady": lambda: learned_vs_euler(fm.FM_FLOW_INV_STEADY)}
 
 
 def main():
