@@ -57,6 +57,25 @@ def spd(n, law, lo, hi, seed, scale_to_unit=False):
     return np.ascontiguousarray(A), Q, lam
 
 
+def spd_reflector(n, lo, hi, seed):
+    """(A, Q, lam) for the largest orders: A = Q diag(lam) Q with the
+    Householder reflector Q = I - 2 v v^T (|v| = 1, symmetric orthogonal),
+    lam ~ U[lo, hi].  A is formed in O(n^2) as diag(lam) - 2 (v w^T + w v^T)
+    + 4 (v^T w) v v^T, w = lam * v; Q is returned dense (the spectral oracle
+    reads rows of it)."""
+    rng = np.random.default_rng(seed)
+    lam = rng.uniform(lo, hi, n)
+    v = rng.standard_normal(n)
+    v /= np.linalg.norm(v)
+    w = lam * v
+    A = -2.0 * (np.outer(v, w) + np.outer(w, v))
+    A += (4.0 * float(v @ w)) * np.outer(v, v)
+    A[np.diag_indices(n)] += lam
+    Q = -2.0 * np.outer(v, v)
+    Q[np.diag_indices(n)] += 1.0
+    return np.ascontiguousarray(A), Q, lam
+
+
 def _cached(name, fn):
     d = os.environ.get("FM_INPUT_CACHE")
     if not d:

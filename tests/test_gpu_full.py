@@ -144,3 +144,22 @@ def test_learned_full_size():
     say("learned n=2048: iters %d, sampled rel err vs oracle %.2e" % (s["iters"], e))
     assert s["learned_restarts"] == 0
     assert e <= 1e-5
+
+
+def test_maximum_order_fp64():
+    """The largest order the interface accepts, with a ragged tail: n = 16383
+    (padded to 16384), homotopy flow, FP64, N = 2 slices of 2 RK4 steps, one
+    iteration; sampled entries against the spectral oracle (A = Q diag(lam) Q
+    with a Householder reflector Q, formed in O(n^2))."""
+    n, N, S, K = 16383, 2, 2, 1
+    A, Q, lam = inputs.spd_reflector(n, 0.3, 2.0, 77)
+    say("maximum order n=%d" % n)
+    st, s, out = _solve(HOMOTOPY, A, "f64", {"T": 1.0, "N": N, "fine_steps": S, "max_iter": K, "tol": 0.0})
+    del A
+    alg, ref = _spectral_parareal(HOMOTOPY, 1.0, Q, lam, N, S, 1, K)
+    rows, cols = _samples(n)
+    rows[-20:] = n - 1                      # the last row and column (next to the padding)
+    cols[-10:] = n - 1
+    e = rel(_sample(out, rows, cols), alg.entries(ref["U"][-1], rows, cols))
+    say("  iters %d, sampled rel err %.2e" % (s["iters"], e))
+    assert s["iters"] == K and e <= 1e-10

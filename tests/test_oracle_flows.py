@@ -234,3 +234,9 @@ def test_laplacian_generators():
     L2 = inputs.laplacian_2d(m)
     mu = 4 * (m + 1) ** 2 * np.sin(np.arange(1, m + 1) * np.pi / (2 * (m + 1))) ** 2
     assert np.allclose(np.linalg.eigvalsh(L2), np.sort(np.add.outer(mu, mu).ravel()), rtol=1e-12)
+
+
+def test_reflector_generator():
+    A, Q, lam = inputs.spd_reflector(40, 0.5, 2.0, 3)
+    assert np.allclose(Q @ Q, np.eye(40), atol=1e-14)
+    assert np.allclose(A, (Q * lam) @ Q, atol=1e-13) and np.array_equal(A, A.T)
