@@ -287,7 +287,10 @@ GemmCfg Flow::pick_cfg(int d, int np) {
   const GemmCfg def = default_cfg(d, np);
   if (force_bm && d == dt) {
     for (const GemmCfg& c : gemm_configs(d))
-      if (c.bm == force_bm && c.bk == force_bk && np % c.bm == 0 && np % c.bk == 0) return c;
+      if (c.bm == force_bm && c.bk == force_bk && np % c.bm == 0 && np % c.bk == 0) {
+        if (verbose) fprintf(stderr, "[fm] tile dt=%d np=%d -> bm=%d bk=%d (forced)\n", d, np, c.bm, c.bk);
+        return c;
+      }
     return def;
   }
   if (!autotune) return def;
@@ -377,9 +380,15 @@ fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char*
   if (kv.count("verbose")) verbose = kv["verbose"] != "0";
   if (kv.count("graph")) use_graph = kv["graph"] != "0";
   if (use_graph) FM_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
-  if (kv.count("tile") && sscanf(kv["tile"].c_str(), "%dx%d", &force_bm, &force_bk) != 2) {
-    set_error("option tile must read <bm>x<bk>");
-    return FM_ERR_INVALID;
+  if (kv.count("tile")) {
+    bool known = sscanf(kv["tile"].c_str(), "%dx%d", &force_bm, &force_bk) == 2;
+    bool found = false;
+    if (known)
+      for (const GemmCfg& c : gemm_configs(dt)) found = found || (c.bm == force_bm && c.bk == force_bk);
+    if (!found) {
+      set_error("option tile must read <bm>x<bk> and name a tile compiled for the flow's dtype");
+      return FM_ERR_INVALID;
+    }
   }
   FM_TRY(ring.init(size_t(256) << 20));
   inst.resize(nb);

@@ -296,26 +296,96 @@ __device__ __forceinline__ void epilogue4(const GItem& it, int64_t idx, int dpos
 // The same epilogue split in two phases, used for the 16-bit products
 // whose epilogue is bound by memory latency: a thread issues the global
 // loads of several element groups (epi_load) before it combines any of them
-// with the products and stores (epi_apply).
+// with the products and stores (epi_apply).  Where the result is a 16-bit
+// operand or the FP32 stage accumulator (the affine product, RK4 stages 1-3)
+// the arithmetic runs in FP32: the product is itself an FP32 accumulation of
+// 16-bit operands, and FP32 keeps everything such an output can hold.  The
+// FP64 state update of the last RK4 stage, the Euler update and every FP64
+// output stay in FP64.  The identity term touches one element of the
+// diagonal tiles only, so it sits behind a branch that other groups skip.
+typedef float f4v __attribute__((ext_vector_type(EV)));
+
+template <class T>
+__device__ __forceinline__ f4v gld4f(const void* p, int64_t idx) {
+  const vec4<T> w = *(gptr<vec4<T>>)((const T*)p + idx);
+  f4v r;
+#pragma unroll
+  for (int e = 0; e < EV; ++e) r[e] = (float)w[e];
+  return r;
+}
+__device__ __forceinline__ void gst4f(void* p, int64_t idx, f4v x) {
+  *(gptr_mut<f4v>)((float*)p + idx) = x;
+}
+template <int DT>
+__device__ __forceinline__ f4v ld_op4f(const void* p, int64_t idx, int64_t np2) {
+  using T = typename Tr<DT>::T;
+  f4v r = gld4f<T>(p, idx);
+  if constexpr (DT == DT_BF16X3) r += gld4f<T>(p, idx + np2);
+  return r;
+}
+// split BF16: hi = bf16(v), lo = bf16(v - hi); v - hi is exact in FP32
+template <int DT>
+__device__ __forceinline__ void st_op4f(void* p, int64_t idx, int64_t np2, f4v x) {
+  using T = typename Tr<DT>::T;
+  vec4<T> w;
+#pragma unroll
+  for (int e = 0; e < EV; ++e) w[e] = (T)x[e];
+  *(gptr_mut<vec4<T>>)((T*)p + idx) = w;
+  if constexpr (DT == DT_BF16X3) {
+    vec4<T> lo;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) lo[e] = (T)(x[e] - (float)w[e]);
+    *(gptr_mut<vec4<T>>)((T*)p + idx + np2) = lo;
+  }
+}
+__device__ __forceinline__ V4 widen(f4v a) {
+  V4 r;
+#pragma unroll
+  for (int e = 0; e < EV; ++e) r.v[e] = (double)a[e];
+  return r;
+}
+__device__ __forceinline__ void add_diag(f4v& v, int dpos, float d) {
+  if (dpos >= 0) {
+#pragma unroll
+    for (int e = 0; e < EV; ++e)
+      if (e == dpos) v[e] += d;
+  }
+}
+__device__ __forceinline__ void add_diag(V4& v, int dpos, double d) {
+  if (dpos >= 0) {
+#pragma unroll
+    for (int e = 0; e < EV; ++e)
+      if (e == dpos) v.v[e] += d;
+  }
+}
+
 struct EpiIn {
-  V4 p, q, r;  // RK4/Euler: state, stage accumulator, E; POLYP/POLYX: in0, in1, in2 (E in r for AFFINE)
+  V4 p, q, r;  // FP64: state (RK4/Euler), POLYP/POLYX inputs, E of an FP64 output
+  f4v kq, er;  // FP32: RK4 stage accumulator, E
 };
 
 template <int DT, int EPI>
 __device__ __forceinline__ EpiIn epi_load(const GItem& it, int64_t idx) {
-  using Acc = typename Tr<DT>::Acc;
   const int64_t np2 = (int64_t)it.np * it.np;
   EpiIn in;
   auto load_e = [&]() -> V4 {
     return (it.flags & F_E_F64) ? gld4<double>(it.in0, idx) : ld_op4<DT>(it.in0, idx, np2);
   };
+  auto load_ef = [&]() -> f4v {
+    return (it.flags & F_E_F64) ? gld4f<double>(it.in0, idx) : ld_op4f<DT>(it.in0, idx, np2);
+  };
   if constexpr (EPI == EPI_AFFINE) {
-    if (!(it.flags & F_E_NONE)) in.r = load_e();
-  } else if constexpr (EPI == EPI_RK4 || EPI == EPI_EULER) {
+    if (!(it.flags & F_E_NONE)) {
+      if (it.flags & F_OUT0_F64) in.r = load_e();
+      else in.er = load_ef();
+    }
+  } else if constexpr (EPI == EPI_RK4) {
+    if (!(it.flags & F_E_NONE)) in.er = load_ef();
+    in.p = gld4<double>(it.x, idx);
+    if (it.stage >= 2) in.kq = gld4f<float>(it.out1, idx);
+  } else if constexpr (EPI == EPI_EULER) {
     if (!(it.flags & F_E_NONE)) in.r = load_e();
     in.p = gld4<double>(it.x, idx);
-    if constexpr (EPI == EPI_RK4)
-      if (it.stage >= 2) in.q = gld4<Acc>(it.out1, idx);
   } else if constexpr (EPI == EPI_POLYP) {
     in.p = ld_op4<DT>(it.in0, idx, np2);
     in.q = ld_op4<DT>(it.in1, idx, np2);
@@ -327,25 +397,54 @@ __device__ __forceinline__ EpiIn epi_load(const GItem& it, int64_t idx) {
   return in;
 }
 
+// af: the four FP32 accumulations of the product
 template <int DT, int EPI>
-__device__ __forceinline__ void epi_apply(const GItem& it, int64_t idx, int dpos, const V4& a, const EpiIn& in) {
-  using Acc = typename Tr<DT>::Acc;
+__device__ __forceinline__ void epi_apply(const GItem& it, int64_t idx, int dpos, const f4v& af, const EpiIn& in) {
+  static_assert(std::is_same<typename Tr<DT>::Acc, float>::value, "16-bit products accumulate in FP32");
   const double* s = it.s;
   const int64_t np2 = (int64_t)it.np * it.np;
   if constexpr (EPI == EPI_AFFINE) {
-    V4 v;
+    if (it.flags & F_OUT0_F64) {
+      const V4 a = widen(af);
+      V4 v;
 #pragma unroll
-    for (int e = 0; e < EV; ++e) v.v[e] = s[0] * a.v[e];
-    if (!(it.flags & F_E_NONE)) {
+      for (int e = 0; e < EV; ++e) v.v[e] = s[0] * a.v[e];
+      if (!(it.flags & F_E_NONE)) {
 #pragma unroll
-      for (int e = 0; e < EV; ++e) v.v[e] += s[1] * in.r.v[e];
+        for (int e = 0; e < EV; ++e) v.v[e] += s[1] * in.r.v[e];
+      }
+      add_diag(v, dpos, s[2]);
+      gst4<double>(it.out0, idx, v);
+    } else {
+      f4v v = (float)s[0] * af;
+      if (!(it.flags & F_E_NONE)) v += (float)s[1] * in.er;
+      add_diag(v, dpos, (float)s[2]);
+      st_op4f<DT>(it.out0, idx, np2, v);
     }
+  } else if constexpr (EPI == EPI_RK4) {
+    f4v k = (float)s[0] * af;
+    if (!(it.flags & F_E_NONE)) k += (float)s[1] * in.er;
+    if (s[3] != 0.0) add_diag(k, dpos, (float)s[3]);  // identity term of the field (dX/dt = I - A X)
+    const double h = s[2];
+    if (it.stage == 4) {  // X <- X + h/6 (k1 + 2 k2 + 2 k3 + k4) in FP64
+      V4 o;
 #pragma unroll
-    for (int e = 0; e < EV; ++e)
-      if (e == dpos) v.v[e] += s[2];
-    if (it.flags & F_OUT0_F64) gst4<double>(it.out0, idx, v);
-    else st_op4<DT>(it.out0, idx, np2, v);
-  } else if constexpr (EPI == EPI_RK4 || EPI == EPI_EULER) {
+      for (int e = 0; e < EV; ++e) o.v[e] = in.p.v[e] + (h / 6.0) * ((double)in.kq[e] + (double)k[e]);
+      gst4<double>(it.x, idx, o);
+      f4v of;
+#pragma unroll
+      for (int e = 0; e < EV; ++e) of[e] = (float)o.v[e];
+      st_op4f<DT>(it.out0, idx, np2, of);
+    } else {
+      gst4f(it.out1, idx, it.stage == 1 ? k : in.kq + 2.0f * k);
+      const float c = (float)(it.stage == 3 ? h : 0.5 * h);
+      f4v o;
+#pragma unroll
+      for (int e = 0; e < EV; ++e) o[e] = (float)in.p.v[e] + c * k[e];
+      st_op4f<DT>(it.out0, idx, np2, o);
+    }
+  } else if constexpr (EPI == EPI_EULER) {
+    const V4 a = widen(af);
     V4 k;
 #pragma unroll
     for (int e = 0; e < EV; ++e) k.v[e] = s[0] * a.v[e];
@@ -353,55 +452,26 @@ __device__ __forceinline__ void epi_apply(const GItem& it, int64_t idx, int dpos
 #pragma unroll
       for (int e = 0; e < EV; ++e) k.v[e] += s[1] * in.r.v[e];
     }
-    if (s[3] != 0.0) {  // identity term of the field (dX/dt = I - A X)
-#pragma unroll
-      for (int e = 0; e < EV; ++e)
-        if (e == dpos) k.v[e] += s[3];
-    }
-    const double h = s[2];
-    const V4& x = in.p;
+    if (s[3] != 0.0) add_diag(k, dpos, s[3]);
     V4 o;
-    if constexpr (EPI == EPI_EULER) {
 #pragma unroll
-      for (int e = 0; e < EV; ++e) o.v[e] = x.v[e] + h * k.v[e];
-      gst4<double>(it.out1, idx, o);
-    } else {
-      void* K = it.out1;
-      if (it.stage == 1) {
-        gst4<Acc>(K, idx, k);
-#pragma unroll
-        for (int e = 0; e < EV; ++e) o.v[e] = x.v[e] + 0.5 * h * k.v[e];
-      } else if (it.stage == 2 || it.stage == 3) {
-        V4 kk = in.q;
-#pragma unroll
-        for (int e = 0; e < EV; ++e) kk.v[e] = kk.v[e] + 2.0 * k.v[e];
-        gst4<Acc>(K, idx, kk);
-        const double c = it.stage == 2 ? 0.5 * h : h;
-#pragma unroll
-        for (int e = 0; e < EV; ++e) o.v[e] = x.v[e] + c * k.v[e];
-      } else {
-#pragma unroll
-        for (int e = 0; e < EV; ++e) o.v[e] = x.v[e] + (h / 6.0) * (in.q.v[e] + k.v[e]);
-        gst4<double>(it.x, idx, o);
-      }
-    }
+    for (int e = 0; e < EV; ++e) o.v[e] = in.p.v[e] + s[2] * k.v[e];
+    gst4<double>(it.out1, idx, o);
     st_op4<DT>(it.out0, idx, np2, o);
   } else if constexpr (EPI == EPI_POLYP) {
+    const V4 a = widen(af);
     V4 v;
 #pragma unroll
     for (int e = 0; e < EV; ++e) v.v[e] = s[1] * in.p.v[e] + s[2] * in.q.v[e] + s[3] * a.v[e];
-#pragma unroll
-    for (int e = 0; e < EV; ++e)
-      if (e == dpos) v.v[e] += s[0];
+    add_diag(v, dpos, s[0]);
     st_op4<DT>(it.out0, idx, np2, v);
     st_op4<DT>(it.out1, idx, np2, a);
   } else {  // EPI_POLYX
+    const V4 a = widen(af);
     V4 v;
 #pragma unroll
     for (int e = 0; e < EV; ++e) v.v[e] = a.v[e] + s[5] * in.p.v[e] + s[6] * in.q.v[e] + s[7] * in.r.v[e];
-#pragma unroll
-    for (int e = 0; e < EV; ++e)
-      if (e == dpos) v.v[e] += s[4];
+    add_diag(v, dpos, s[4]);
     gst4<double>(it.out1, idx, v);
     st_op4<DT>(it.out0, idx, np2, v);
   }
@@ -433,7 +503,24 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
   constexpr int NQ = 64 / MI;            // lane groups along k
   constexpr int KC = NQ * V;             // k per chunk
   constexpr int W = 16 / sizeof(T);      // elements per 16-byte chunk
-  constexpr int PADA = 16 / sizeof(T);
+  // global prefetch depth in K tiles: the 16-bit K tiles of the 128-wide
+  // tiles are short next to the memory latency, so their loads are issued
+  // two tiles ahead (the 256-wide tiles have no registers for a second set)
+  constexpr int PF = (DT == DT_F64 || DT == DT_F32 || BM > 128) ? 1 : 2;
+  // 16-bit A tiles fetched one K tile ahead go from global memory straight
+  // into LDS (buffer loads with the LDS flag): no staging registers and no
+  // LDS store instructions.  Such a load writes the 16-byte chunks of a wave
+  // to 1 KB of consecutive LDS, so the tile is stored unpadded, 16-byte chunk
+  // j of row r at chunk position j ^ aswz(r) of that row: the lane that fills
+  // a position loads the chunk that belongs there, and the fragment reads
+  // (32 rows at one chunk) fall on distinct banks.
+  constexpr bool ADMA = DT != DT_F64 && DT != DT_F32 && PF == 1;
+  constexpr int CPR = BK / (16 / (int)sizeof(T));  // 16-byte chunks per A row
+  constexpr int CPR_SH = CPR == 8 ? 3 : CPR == 4 ? 2 : CPR == 2 ? 1 : 0;
+  static_assert(!ADMA || CPR == 4 || CPR == 8, "A swizzle assumes 4 or 8 chunks per row");
+  static_assert(!ADMA || TR::V == 16 / (int)sizeof(T), "A fragment reads assume one chunk per k-vector");
+  auto aswz = [](int r) { return (r ^ (r >> CPR_SH)) & (CPR - 1); };
+  constexpr int PADA = ADMA ? 0 : 16 / (int)sizeof(T);
   constexpr int LDA_S = BK + PADA;       // LDS row stride of A (elements)
   constexpr int A_CHUNKS = BM * BK / W;  // 16-byte chunks of an A tile
   constexpr int B_BLOCKS = (BK / V) * (BN / W);
@@ -455,10 +542,6 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
   constexpr int SUBV = (DT == DT_F64 || DT == DT_F32) ? 2 : V;
   constexpr int SUB = V / SUBV;
   constexpr int NSTEP = (BK / KC) * SUB;
-  // global prefetch depth in K tiles: the 16-bit K tiles of the 128-wide
-  // tiles are short next to the memory latency, so their loads are issued
-  // two tiles ahead (the 256-wide tiles have no registers for a second set)
-  constexpr int PF = (DT == DT_F64 || DT == DT_F32 || BM > 128) ? 1 : 2;
   static_assert(NSTEP % 2 == 0, "pipeline steps per K tile must be even");
   // B column swizzle inside aligned groups of G columns (G columns = 128 bytes
   // of k-vectors): a thread stores W adjacent columns, so without it the lanes
@@ -471,7 +554,9 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
   // one LDS block: two stages of A and B tiles during the K loop, reused
   // by the epilogue to stage accumulators
   constexpr int A_STAGE = BM * LDA_S, B_STAGE = BK * BN;
-  constexpr int SMEM = 2 * (A_STAGE + B_STAGE) * (int)sizeof(T);
+  constexpr int SMEM_K = 2 * (A_STAGE + B_STAGE) * (int)sizeof(T);
+  constexpr int SMEM_E = 2 * TR::MI * (BN + 16 / (int)sizeof(typename TR::Acc)) * (int)sizeof(typename TR::Acc);
+  constexpr int SMEM = SMEM_K > SMEM_E ? SMEM_K : SMEM_E;
   __shared__ __attribute__((aligned(16))) char smem[SMEM];
   T (*As)[A_STAGE] = reinterpret_cast<T (*)[A_STAGE]>(smem);
   T (*Bs)[B_STAGE] = reinterpret_cast<T (*)[B_STAGE]>(smem + 2 * A_STAGE * sizeof(T));
@@ -535,7 +620,7 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
         for (int v = 0; v < NACC; ++v) acc[i][j][v] = 0;
 
     // PF register staging sets: tile kt's global loads land in set kt % PF
-    G16 ra[PF][A_PER_T];
+    G16 ra[PF][ADMA ? 1 : A_PER_T];
     G16 rb[PF][B_PER_T][VR];
 
     const int64_t np2 = (int64_t)np * np;
@@ -544,7 +629,7 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
     // per-lane byte offsets are loop-invariant and small, and a resource's
     // record count is the exact extent of the tile's panel, so a load can
     // never leave it (out-of-range buffer loads return zero).
-    auto gload = [&](int kt, int set) {
+    auto gload = [&](int kt, int set, int dbuf) {
       // segment 0: (A_hi, B_hi); 1: (A_hi, B_lo); 2: (A_lo, B_hi)
       const int seg = kt / nkps;
       const int k0 = (kt - seg * nkps) * BK;
@@ -554,12 +639,25 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
           const_cast<T*>(As_g), (short)0, ((BM - 1) * np + BK) * (int)sizeof(T), 0x00020000);
       const __amdgpu_buffer_rsrc_t rb_rs = __builtin_amdgcn_make_buffer_rsrc(
           const_cast<T*>(Bs_g), (short)0, ((BK - 1) * np + BN) * (int)sizeof(T), 0x00020000);
+      if constexpr (ADMA) {
+        // position p = NT*u + tid of LDS buffer dbuf (wave-uniform base, lane
+        // offset 16 bytes per lane) receives chunk (p % CPR) ^ aswz(row)
 #pragma unroll
-      for (int u = 0; u < A_PER_T; ++u) {
-        const int c = tid + NT * u;
-        const int r = c / (BK / W), cc = c % (BK / W);
-        ra[set][u] = __builtin_bit_cast(G16, __builtin_amdgcn_raw_buffer_load_b128(
-                                            ra_rs, (r * np + cc * W) * (int)sizeof(T), 0, 0));
+        for (int u = 0; u < A_PER_T; ++u) {
+          const int p = tid + NT * u;
+          const int r = p / CPR, cc = (p % CPR) ^ aswz(r);
+          __attribute__((address_space(3))) void* dst =
+              (__attribute__((address_space(3))) void*)(&As[dbuf][(NT * u + wave * 64) * W]);
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(ra_rs, dst, 16, (r * np + cc * W) * (int)sizeof(T), 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < A_PER_T; ++u) {
+          const int c = tid + NT * u;
+          const int r = c / (BK / W), cc = c % (BK / W);
+          ra[set][u] = __builtin_bit_cast(G16, __builtin_amdgcn_raw_buffer_load_b128(
+                                              ra_rs, (r * np + cc * W) * (int)sizeof(T), 0, 0));
+        }
       }
 #pragma unroll
       for (int u = 0; u < B_PER_T; ++u) {
@@ -573,11 +671,13 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
       }
     };
     auto lstore = [&](int buf, int set) {
+      if constexpr (!ADMA) {
 #pragma unroll
-      for (int u = 0; u < A_PER_T; ++u) {
-        const int c = tid + NT * u;
-        const int r = c / (BK / W), cc = c % (BK / W);
-        *(G16*)(&As[buf][r * LDA_S + cc * W]) = ra[set][u];
+        for (int u = 0; u < A_PER_T; ++u) {
+          const int c = tid + NT * u;
+          const int r = c / (BK / W), cc = c % (BK / W);
+          *(G16*)(&As[buf][r * LDA_S + cc * W]) = ra[set][u];
+        }
       }
       // The B store addresses are recomputed at every store from an opaque
       // copy of the thread index: hoisted out of the K loop they would hold
@@ -615,8 +715,13 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
     auto read_frag = [&](FV (&fa)[RM], FV (&fb)[RN], int buf, int sidx) {
       const int ch = sidx / SUB, sub = sidx % SUB;
 #pragma unroll
-      for (int i = 0; i < RM; ++i)
-        fa[i] = *(const FV*)(&As[buf][(wr * WM + i * MI + lr) * LDA_S + ch * KC + lq * V + sub * SUBV]);
+      for (int i = 0; i < RM; ++i) {
+        const int r = wr * WM + i * MI + lr;
+        if constexpr (ADMA)  // 16-bit: one lane's k-vector is one chunk (V == W)
+          fa[i] = *(const FV*)(&As[buf][r * LDA_S + ((ch * NQ + lq) ^ aswz(r)) * W]);
+        else
+          fa[i] = *(const FV*)(&As[buf][r * LDA_S + ch * KC + lq * V + sub * SUBV]);
+      }
 #pragma unroll
       for (int j = 0; j < RN; ++j)
         fb[j] = *(const FV*)(&Bs[buf][((ch * NQ + lq) * BN + bswz(wc * WN + j * MI + lr)) * V + sub * SUBV]);
@@ -662,7 +767,7 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
           lstore(cur ^ 1, set);
           __syncthreads();
           read_frag(fa_n, fb_n, cur ^ 1, 0);
-          gload(min(kt + 1 + PF, nk - 1), set);
+          gload(min(kt + 1 + PF, nk - 1), set, cur);  // A (ADMA): into the buffer just released
         }
         __builtin_amdgcn_sched_barrier(0);
         mfma_step(fa_c, fb_c);
@@ -671,10 +776,10 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
     };
 
     __syncthreads();  // the previous output tile's epilogue may still read LDS
-    gload(0, 0);
+    gload(0, 0, 0);
     lstore(0, 0);
-    gload(min(1, nk - 1), PF - 1);
-    if (PF == 2) gload(min(2, nk - 1), 0);
+    gload(min(1, nk - 1), PF - 1, 1);
+    if (PF == 2) gload(min(2, nk - 1), 0, 0);
     __syncthreads();
     read_frag(fa0, fb0, 0, 0);
     if constexpr (PF == 1) {
@@ -692,6 +797,8 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
     // global traffic is coalesced and the accumulators are only ever
     // indexed statically.
     {
+      // the clamped A reload of the last K tile may still be landing in LDS
+      if constexpr (ADMA) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
       using Acc = typename TR::Acc;
       constexpr int CROWS = 2 * MI;
       constexpr int CLD = BN + 16 / (int)sizeof(Acc);
@@ -745,11 +852,9 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
             const int rr = (e * EV) / BN, cc = (e * EV) % BN;
             const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
             const int gc = col0 + cc;
-            V4 a;
-#pragma unroll
-            for (int q = 0; q < EV; ++q) a.v[q] = (double)Cs[rr * CLD + cc + q];
+            const f4v af = *(const f4v*)&Cs[rr * CLD + cc];
             const int dpos = (gr >= gc && gr < gc + EV && gr < n_valid) ? gr - gc : -1;
-            epi_apply<DT, EPI>(it, idx[g], dpos, a, in[g]);
+            epi_apply<DT, EPI>(it, idx[g], dpos, af, in[g]);
           }
         }
       }
