@@ -520,6 +520,18 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
   static_assert(!ADMA || CPR == 4 || CPR == 8, "A swizzle assumes 4 or 8 chunks per row");
   static_assert(!ADMA || TR::V == 16 / (int)sizeof(T), "A fragment reads assume one chunk per k-vector");
   auto aswz = [](int r) { return (r ^ (r >> CPR_SH)) & (CPR - 1); };
+  // The 256 x 32 16-bit tiles go further: B comes by LDS DMA as well, into
+  // a ring of NS stages, so NS - 1 K tiles of loads are in flight while one
+  // is computed.  B keeps its row-major global layout in LDS (16-byte chunk
+  // j of k-row r at position j ^ bsw(r)); each lane's eight k-values of one
+  // column are gathered by two transposing LDS reads (ds_read_b64_tr_b16:
+  // within 16 lanes, lane i receives element i % 4 of the 8-byte reads of
+  // lanes 4j + i / 4, j = 0..3).  bsw(r) = 5 (r mod 4) puts the 16 lanes of
+  // such a read (4 rows x 32 bytes) on distinct banks (checked by
+  // enumeration in a 32-bank and in a 64-bank model).
+  constexpr bool RING = ADMA && BM == 256 && BK == 32;
+  constexpr int NS = RING ? 4 : 2;  // LDS stages
+  auto bsw = [](int r) { return 5 * (r & 3); };
   constexpr int PADA = ADMA ? 0 : 16 / (int)sizeof(T);
   constexpr int LDA_S = BK + PADA;       // LDS row stride of A (elements)
   constexpr int A_CHUNKS = BM * BK / W;  // 16-byte chunks of an A tile
@@ -528,6 +540,9 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
   static_assert(A_CHUNKS % NT == 0, "A tile must split evenly over the threads");
   static_assert(B_BLOCKS <= NT || B_BLOCKS % NT == 0, "B tile split");
   constexpr int A_PER_T = A_CHUNKS / NT;
+  constexpr int BR_PER_T = BK * BN / W / NT;  // B chunks per thread (ring)
+  static_assert(!RING || (BK * BN / W) % NT == 0, "B tile split (ring)");
+  static_assert(!RING || (BN / W) == 32, "the B swizzle assumes 32 chunks per k-row");
   constexpr int B_PER_T = B_BLOCKS >= NT ? B_BLOCKS / NT : 1;
   // When the tile has fewer B blocks (V rows x 16 bytes) than threads, the
   // RSPLIT threads of a block share its rows (VR each) so that every thread
@@ -554,12 +569,12 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
   // one LDS block: two stages of A and B tiles during the K loop, reused
   // by the epilogue to stage accumulators
   constexpr int A_STAGE = BM * LDA_S, B_STAGE = BK * BN;
-  constexpr int SMEM_K = 2 * (A_STAGE + B_STAGE) * (int)sizeof(T);
+  constexpr int SMEM_K = NS * (A_STAGE + B_STAGE) * (int)sizeof(T);
   constexpr int SMEM_E = 2 * TR::MI * (BN + 16 / (int)sizeof(typename TR::Acc)) * (int)sizeof(typename TR::Acc);
   constexpr int SMEM = SMEM_K > SMEM_E ? SMEM_K : SMEM_E;
   __shared__ __attribute__((aligned(16))) char smem[SMEM];
   T (*As)[A_STAGE] = reinterpret_cast<T (*)[A_STAGE]>(smem);
-  T (*Bs)[B_STAGE] = reinterpret_cast<T (*)[B_STAGE]>(smem + 2 * A_STAGE * sizeof(T));
+  T (*Bs)[B_STAGE] = reinterpret_cast<T (*)[B_STAGE]>(smem + NS * A_STAGE * sizeof(T));
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -659,15 +674,26 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
                                               ra_rs, (r * np + cc * W) * (int)sizeof(T), 0, 0));
         }
       }
+      if constexpr (RING) {
 #pragma unroll
-      for (int u = 0; u < B_PER_T; ++u) {
-        const int blk = RSPLIT > 1 ? tid % B_BLOCKS : tid + NT * u;
-        const int r0 = RSPLIT > 1 ? (tid / B_BLOCKS) * VR : 0;
-        const int kb = blk / (BN / W), cb = blk % (BN / W);
+        for (int u = 0; u < BR_PER_T; ++u) {
+          const int p = tid + NT * u;
+          const int r = p / (BN / W), cc = (p % (BN / W)) ^ bsw(r);
+          __attribute__((address_space(3))) void* dst =
+              (__attribute__((address_space(3))) void*)(&Bs[dbuf][(NT * u + wave * 64) * W]);
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rb_rs, dst, 16, (r * np + cc * W) * (int)sizeof(T), 0, 0, 0);
+        }
+      } else {
 #pragma unroll
-        for (int r = 0; r < VR; ++r)
-          rb[set][u][r] = __builtin_bit_cast(G16, __builtin_amdgcn_raw_buffer_load_b128(
-                                                 rb_rs, ((kb * V + r0 + r) * np + cb * W) * (int)sizeof(T), 0, 0));
+        for (int u = 0; u < B_PER_T; ++u) {
+          const int blk = RSPLIT > 1 ? tid % B_BLOCKS : tid + NT * u;
+          const int r0 = RSPLIT > 1 ? (tid / B_BLOCKS) * VR : 0;
+          const int kb = blk / (BN / W), cb = blk % (BN / W);
+#pragma unroll
+          for (int r = 0; r < VR; ++r)
+            rb[set][u][r] = __builtin_bit_cast(G16, __builtin_amdgcn_raw_buffer_load_b128(
+                                                   rb_rs, ((kb * V + r0 + r) * np + cb * W) * (int)sizeof(T), 0, 0));
+        }
       }
     };
     auto lstore = [&](int buf, int set) {
@@ -722,9 +748,42 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
         else
           fa[i] = *(const FV*)(&As[buf][r * LDA_S + ch * KC + lq * V + sub * SUBV]);
       }
+      if constexpr (RING) {
+        // lane (g, jj, a) = (lane / 16, lane / 4 % 4, lane % 4) supplies row
+        // r (then r + 4), columns c .. c+3; lane l receives k-rows
+        // ch*KC + 8 (l / 32) + 0..7 of column wc*WN + j*MI + l % 32.  The
+        // reads are written as assembly that waits for them in the same
+        // block: through the builtin the compiler would first wait for every
+        // LDS DMA in flight, which would drain the ring at every step.
+        static_assert(RN == 2, "the transposing reads are written for two B fragments");
+        typedef short s4v __attribute__((ext_vector_type(4)));
+        typedef short s8v __attribute__((ext_vector_type(8)));
+        const int g = lane >> 4, jj = (lane >> 2) & 3, a = lane & 3;
+        const int r = ch * KC + 8 * (g >> 1) + jj;
+        unsigned ad[RN];
 #pragma unroll
-      for (int j = 0; j < RN; ++j)
-        fb[j] = *(const FV*)(&Bs[buf][((ch * NQ + lq) * BN + bswz(wc * WN + j * MI + lr)) * V + sub * SUBV]);
+        for (int j = 0; j < RN; ++j) {
+          const int c = wc * WN + j * MI + 16 * (g & 1) + 4 * a;
+          ad[j] = (unsigned)(size_t)(__attribute__((address_space(3))) const T*)(
+              &Bs[buf][r * BN + ((c / W) ^ bsw(r)) * W + (c % W)]);
+        }
+        s4v lo0, hi0, lo1, hi1;
+        asm volatile(
+            "ds_read_b64_tr_b16 %0, %4\n\t"
+            "ds_read_b64_tr_b16 %1, %4 offset:%6\n\t"
+            "ds_read_b64_tr_b16 %2, %5\n\t"
+            "ds_read_b64_tr_b16 %3, %5 offset:%6\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(lo0), "=&v"(hi0), "=&v"(lo1), "=&v"(hi1)
+            : "v"(ad[0]), "v"(ad[1]), "n"(4 * BN * (int)sizeof(T))
+            : "memory");
+        fb[0] = __builtin_bit_cast(FV, (s8v)__builtin_shufflevector(lo0, hi0, 0, 1, 2, 3, 4, 5, 6, 7));
+        fb[1] = __builtin_bit_cast(FV, (s8v)__builtin_shufflevector(lo1, hi1, 0, 1, 2, 3, 4, 5, 6, 7));
+      } else {
+#pragma unroll
+        for (int j = 0; j < RN; ++j)
+          fb[j] = *(const FV*)(&Bs[buf][((ch * NQ + lq) * BN + bswz(wc * WN + j * MI + lr)) * V + sub * SUBV]);
+      }
     };
     auto mfma_step = [&](const FV (&fa)[RM], const FV (&fb)[RN]) {
       if constexpr (DT == DT_F64 || DT == DT_F32) {
@@ -775,7 +834,51 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
       });
     };
 
+    // Ring K loop: tile kt sits in stage kt % NS.  At its last step a wave
+    // waits until only the loads of tiles kt+2 .. kt+NS-1 are outstanding
+    // (its own loads of tile kt+1 have landed) and its LDS reads are done;
+    // the barrier then publishes tile kt+1 to all waves and frees stage
+    // kt % NS, which is refilled with tile kt+NS at once.  Every thread
+    // issues LPT loads per tile in every K tile (clamped tile index after
+    // the last), so the outstanding count is the same everywhere.
+    constexpr int LPT = A_PER_T + BR_PER_T;
+    auto ring_sync = [](auto n_c) {
+      asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(decltype(n_c)::value) : "memory");
+    };
+    auto ktile_ring = [&](int kt) {
+      const int cur = kt & (NS - 1), nxt = (kt + 1) & (NS - 1);
+      static_for(std::make_integer_sequence<int, NSTEP>(), [&](auto s_c) {
+        constexpr int sidx = decltype(s_c)::value;
+        FV(&fa_c)[RM] = (sidx & 1) ? fa1 : fa0;
+        FV(&fb_c)[RN] = (sidx & 1) ? fb1 : fb0;
+        FV(&fa_n)[RM] = (sidx & 1) ? fa0 : fa1;
+        FV(&fb_n)[RN] = (sidx & 1) ? fb0 : fb1;
+        // the MFMAs go first: the fragment reads of the next step wait for
+        // their data, which the other wave of the SIMD covers
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_step(fa_c, fb_c);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (sidx + 1 < NSTEP) {
+          read_frag(fa_n, fb_n, cur, sidx + 1);
+        } else {
+          ring_sync(std::integral_constant<int, (NS - 2) * LPT>());
+          read_frag(fa_n, fb_n, nxt, 0);
+          gload(min(kt + NS, nk - 1), 0, cur);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    };
+
     __syncthreads();  // the previous output tile's epilogue may still read LDS
+    if constexpr (RING) {
+      static_for(std::make_integer_sequence<int, NS>(), [&](auto s_c) {
+        constexpr int st = decltype(s_c)::value;
+        gload(min(st, nk - 1), 0, st);
+      });
+      ring_sync(std::integral_constant<int, (NS - 1) * LPT>());
+      read_frag(fa0, fb0, 0, 0);
+      for (int kt = 0; kt < nk; ++kt) ktile_ring(kt);
+    } else {
     gload(0, 0, 0);
     lstore(0, 0);
     gload(min(1, nk - 1), PF - 1, 1);
@@ -789,6 +892,7 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
         ktile(std::integral_constant<int, 0>(), kt);
         if (kt + 1 < nk) ktile(std::integral_constant<int, 1>(), kt + 1);  // nk is odd only for 64-wide tiles
       }
+    }
     }
 
     // Fused epilogue, staged through LDS in RM passes: in pass i every wave
