@@ -66,8 +66,10 @@ typedef enum {
 
 /* Arithmetic of the dense products of the propagators (MFMA input type).  The
  * parareal iterates, the correction sum, the residual and the refinement are
- * always FP64; with FM_F32/BF16/F16/BF16X3 products accumulate in FP32 and the
- * propagator state is kept in FP64 between products.  FM_BF16X3 splits each
+ * always FP64; with FM_F32/BF16/F16/BF16X3 products accumulate in FP32.  The
+ * fine propagator's state is FP64 between products for FM_F64/F32 and FP32
+ * inside one fine propagation for the 16-bit types (narrowed from and widened
+ * back to the FP64 slice state around it).  FM_BF16X3 splits each
  * operand into BF16 hi + lo parts and forms A_hi B_hi + A_hi B_lo + A_lo B_hi
  * (three BF16 MFMA products, ~16 significant bits). */
 typedef enum { FM_F64 = 0, FM_F32 = 1, FM_BF16 = 2, FM_F16 = 3, FM_BF16X3 = 4 } fm_dtype;

@@ -159,6 +159,7 @@ Flow::~Flow() {
   ring.release();
   work.release();
   prop.release();
+  if (x32buf) (void)hipFree(x32buf);
   if (part) (void)hipFree(part);
   if (hredu) (void)hipHostFree(hredu);
 }
@@ -179,6 +180,17 @@ fm_status Flow::ensure_part(size_t count) {
   part = nullptr;
   FM_HIP(hipMalloc((void**)&part, count * sizeof(double)));
   part_cap = count;
+  return FM_OK;
+}
+// Growing the buffer frees the old one: hipFree waits for the device, so no
+// launch still reads it.
+fm_status Flow::ensure_x32(size_t count) {
+  if (count <= x32_cap) return FM_OK;
+  if (x32buf) (void)hipFree(x32buf);
+  x32buf = nullptr;
+  x32_cap = 0;
+  FM_HIP(hipMalloc((void**)&x32buf, count * sizeof(float)));
+  x32_cap = count;
   return FM_OK;
 }
 fm_status Flow::ensure_hredu(size_t count) {
@@ -259,7 +271,8 @@ static double time_cfg(const GemmCfg& c, int np, int nb, void* A, void* B, void*
     r.b = g.out0;
     r.out0 = (char*)C + (size_t)(nb + j) * np2 * esz;  // own next-stage operand buffer
     r.out1 = (char*)Kacc + (size_t)j * np2 * asz;
-    r.x = X + (size_t)j * np2;
+    r.x = X + (size_t)j * np2;  // FP64-sized: holds the FP32 state of 16-bit products too
+    if (c.dt == DT_BF16 || c.dt == DT_F16 || c.dt == DT_BF16X3) r.flags |= F_X_F32;
     r.stage = 1;
     r.s[0] = -1.0;
     r.s[2] = 1e-3;
@@ -519,10 +532,31 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
   const int units = euler ? steps / 2 : steps;
   const bool tail = euler && (steps % 2 == 1);
   const int fepi = euler ? EPI_EULER : EPI_RK4;
+  // 16-bit products with RK4: the steps carry the state in FP32 (a stage
+  // increment is an FP32 accumulation of 16-bit operands, so FP64 would hold
+  // digits no step produces, at 20 more bytes per element and step); it is
+  // narrowed from and widened back to the slot's FP64 state around the steps.
+  const bool x32 = !euler && (dt == DT_BF16 || dt == DT_F16 || dt == DT_BF16X3);
+  std::vector<float*> xs(slots.size(), nullptr);
+  std::vector<CastItem> narrow, widen;
+  if (x32) {
+    size_t need = 0;
+    for (const FineSlot& sl : slots) need += ((size_t)inst[sl.inst].np * inst[sl.inst].np + 63) / 64 * 64;
+    FM_TRY(ensure_x32(need));
+    size_t off = 0;
+    for (size_t k = 0; k < slots.size(); ++k) {
+      const int64_t np2 = (int64_t)inst[slots[k].inst].np * inst[slots[k].inst].np;
+      xs[k] = x32buf + off;
+      off += ((size_t)np2 + 63) / 64 * 64;
+      narrow.push_back(CastItem{slots[k].x, xs[k], np2, 1, 0});
+      widen.push_back(CastItem{xs[k], slots[k].x, np2, 0, 0});
+    }
+  }
   std::vector<GItem> l1[4], l2[4];
   std::vector<int> i1[4], i2[4];
   for (int s = 0; s < nst; ++s) {
-    for (const FineSlot& sl : slots) {
+    for (size_t k = 0; k < slots.size(); ++k) {
+      const FineSlot& sl = slots[k];
       const Inst& in = inst[sl.inst];
       void* ycur = (s % 2 == 0) ? sl.ya : sl.yb;
       void* ynext = (s % 2 == 0) ? sl.yb : sl.ya;
@@ -540,7 +574,8 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
       field_item(g, in, ycur, sl.p);
       g.out0 = ynext;
       g.out1 = euler ? (void*)sl.x : sl.kacc;
-      g.x = sl.x;
+      g.x = x32 ? (double*)(void*)xs[k] : sl.x;
+      if (x32) g.flags |= F_X_F32;
       g.stage = s + 1;
       g.s[2] = sl.h;
       l2[s].push_back(g);
@@ -564,8 +599,22 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
     size_t need = 0;
     for (int s = 0; s < nst; ++s)
       need += (l1[s].size() + l2[s].size()) * (sizeof(GItem) + sizeof(int)) + 8 * 512;
+    need += 2 * (slots.size() * sizeof(CastItem) + 512);
     FM_TRY(reserve_ring(need, st));
   }
+  const CastItem* d_widen = nullptr;
+  if (x32) {
+    void* dn = nullptr;
+    void* dw = nullptr;
+    FM_TRY(push(narrow.data(), narrow.size() * sizeof(CastItem), &dn, st));
+    FM_TRY(push(widen.data(), widen.size() * sizeof(CastItem), &dw, st));
+    FM_HIP(launch_cast((const CastItem*)dn, (int)narrow.size(), st));
+    d_widen = (const CastItem*)dw;
+  }
+  auto widen_back = [&]() -> fm_status {
+    if (x32) FM_HIP(launch_cast(d_widen, (int)widen.size(), st));
+    return FM_OK;
+  };
   auto prepare = [&](std::vector<GItem>& items, const std::vector<int>& ii, int epi) -> fm_status {
     if (items.empty()) return FM_OK;
     std::map<std::pair<int, int>, std::vector<int>> groups;
@@ -645,7 +694,8 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
     pending_exec.push_back(ge);
     pending_stream.push_back(st);
     for (int u = 0; u < units; ++u) FM_HIP(hipGraphLaunch(ge, st));
-    return launch_tail();
+    FM_TRY(launch_tail());
+    return widen_back();
   }
   for (int u = 0; u < units; ++u)
     for (const Launch& L : seq) {
@@ -664,6 +714,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
       }
     }
   FM_TRY(launch_tail());
+  FM_TRY(widen_back());
   if (timing && phase_ev >= 0) {
     FM_HIP(hipEventRecord(ev[phase_ev + 1], st));
     phase_pairs.push_back(phase_ev);

@@ -124,6 +124,8 @@ struct Flow {
   Arena prop;      // propagator workspace (fm_fine/coarse_propagate)
   double* part = nullptr;   // reduction partials
   size_t part_cap = 0;
+  float* x32buf = nullptr;  // FP32 states of the 16-bit fine solves
+  size_t x32_cap = 0;
   double* hredu = nullptr;  // pinned host copy of reduced triples
   size_t hredu_cap = 0;
 
@@ -155,6 +157,7 @@ struct Flow {
   // make sure `bytes` of item lists can be pushed without an intermediate reset
   fm_status reserve_ring(size_t bytes, hipStream_t st);
   fm_status ensure_part(size_t count);
+  fm_status ensure_x32(size_t count);
   // batched zero-padded copies in (pad = 1) or out (pad = 0) of the library layout
   fm_status pad_copy(const std::vector<double*>& dst, const std::vector<const double*>& src, int pad,
                      hipStream_t st);

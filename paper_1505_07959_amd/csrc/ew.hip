@@ -64,6 +64,20 @@ __global__ void k_prep(const PrepItem* __restrict__ items, const int* __restrict
   }
 }
 
+__global__ void k_cast(const CastItem* __restrict__ items) {
+  const CastItem it = items[blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (it.narrow) {
+    const double* s = (const double*)it.src;
+    float* d = (float*)it.dst;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < it.count; e += stride) d[e] = (float)s[e];
+  } else {
+    const float* s = (const float*)it.src;
+    double* d = (double*)it.dst;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < it.count; e += stride) d[e] = (double)s[e];
+  }
+}
+
 template <class T>
 __global__ void k_fill(T* __restrict__ dst, int64_t count) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
@@ -441,6 +455,12 @@ hipError_t launch_prep(const PrepItem* items, int nitems, int dt, const int* liv
     case DT_BF16X3: hipLaunchKernelGGL((k_prep<__bf16, true>), g, b, 0, st, items, live); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_cast(const CastItem* items, int nitems, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cast, dim3(256, nitems), dim3(EW_THREADS), 0, st, items);
   return hipGetLastError();
 }
 

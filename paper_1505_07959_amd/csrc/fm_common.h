@@ -40,6 +40,7 @@ enum : int {
   F_OUT0_F64 = 1,   // out0 is FP64 (else operand type)
   F_E_F64 = 2,      // in0 is FP64 (else operand type) -- EPI_AFFINE/RK4/EULER
   F_E_NONE = 4,     // no E term
+  F_X_F32 = 8,      // the RK4 state x is FP32 (16-bit products only)
 };
 
 // One matrix product of a grouped launch.  All matrices are np x np,
@@ -52,7 +53,7 @@ struct GItem {
   const void* in0;
   const void* in1;
   const void* in2;
-  double* x;        // FP64 state for EPI_RK4 / EPI_EULER
+  double* x;        // state for EPI_RK4 / EPI_EULER: FP64, or FP32 with F_X_F32
   double s[8];
   int np;
   int stage;
@@ -133,6 +134,16 @@ struct PrepItem {
   int pad_;
 };
 hipError_t launch_prep(const PrepItem* items, int nitems, int dt, const int* live, hipStream_t st);
+// Batched precision change of whole matrices: FP64 -> FP32 (narrow = 1,
+// round to nearest) or FP32 -> FP64 (narrow = 0, exact).
+struct CastItem {
+  const void* src;
+  void* dst;
+  int64_t count;
+  int narrow;
+  int pad_;
+};
+hipError_t launch_cast(const CastItem* items, int nitems, hipStream_t st);
 // Deterministic reduction of `nitems` x nblk partial pairs into per-item
 // (||d||^2, ||u||^2, nonfinite) triples in out[3*j].
 hipError_t launch_reduce_pairs(const double* part, int nitems, int nblk, double* out, hipStream_t st);

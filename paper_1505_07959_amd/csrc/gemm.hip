@@ -296,12 +296,11 @@ __device__ __forceinline__ void epilogue4(const GItem& it, int64_t idx, int dpos
 // The same epilogue split in two phases, used for the 16-bit products
 // whose epilogue is bound by memory latency: a thread issues the global
 // loads of several element groups (epi_load) before it combines any of them
-// with the products and stores (epi_apply).  Where the result is a 16-bit
-// operand or the FP32 stage accumulator (the affine product, RK4 stages 1-3)
-// the arithmetic runs in FP32: the product is itself an FP32 accumulation of
-// 16-bit operands, and FP32 keeps everything such an output can hold.  The
-// FP64 state update of the last RK4 stage, the Euler update and every FP64
-// output stay in FP64.  The identity term touches one element of the
+// with the products and stores (epi_apply).  The affine product and the RK4
+// stage update run in FP32, on an FP32 state (F_X_F32): the product is
+// itself an FP32 accumulation of 16-bit operands, and FP32 keeps everything
+// such a step produces.  The Euler update (FP64 state) and every FP64 output
+// stay in FP64.  The identity term touches one element of the
 // diagonal tiles only, so it sits behind a branch that other groups skip.
 typedef float f4v __attribute__((ext_vector_type(EV)));
 
@@ -362,6 +361,7 @@ __device__ __forceinline__ void add_diag(V4& v, int dpos, double d) {
 struct EpiIn {
   V4 p, q, r;  // FP64: state (RK4/Euler), POLYP/POLYX inputs, E of an FP64 output
   f4v kq, er;  // FP32: RK4 stage accumulator, E
+  f4v xf;      // FP32 RK4 state (F_X_F32)
 };
 
 template <int DT, int EPI>
@@ -381,7 +381,7 @@ __device__ __forceinline__ EpiIn epi_load(const GItem& it, int64_t idx) {
     }
   } else if constexpr (EPI == EPI_RK4) {
     if (!(it.flags & F_E_NONE)) in.er = load_ef();
-    in.p = gld4<double>(it.x, idx);
+    in.xf = gld4f<float>(it.x, idx);  // 16-bit products: FP32 state (F_X_F32)
     if (it.stage >= 2) in.kq = gld4f<float>(it.out1, idx);
   } else if constexpr (EPI == EPI_EULER) {
     if (!(it.flags & F_E_NONE)) in.r = load_e();
@@ -425,23 +425,15 @@ __device__ __forceinline__ void epi_apply(const GItem& it, int64_t idx, int dpos
     f4v k = (float)s[0] * af;
     if (!(it.flags & F_E_NONE)) k += (float)s[1] * in.er;
     if (s[3] != 0.0) add_diag(k, dpos, (float)s[3]);  // identity term of the field (dX/dt = I - A X)
+    // the state of a fine solve with 16-bit products is FP32 (F_X_F32)
     const double h = s[2];
-    if (it.stage == 4) {  // X <- X + h/6 (k1 + 2 k2 + 2 k3 + k4) in FP64
-      V4 o;
-#pragma unroll
-      for (int e = 0; e < EV; ++e) o.v[e] = in.p.v[e] + (h / 6.0) * ((double)in.kq[e] + (double)k[e]);
-      gst4<double>(it.x, idx, o);
-      f4v of;
-#pragma unroll
-      for (int e = 0; e < EV; ++e) of[e] = (float)o.v[e];
-      st_op4f<DT>(it.out0, idx, np2, of);
+    if (it.stage == 4) {  // X <- X + h/6 (k1 + 2 k2 + 2 k3 + k4)
+      const f4v o = in.xf + (float)(h / 6.0) * (in.kq + k);
+      gst4f(it.x, idx, o);
+      st_op4f<DT>(it.out0, idx, np2, o);
     } else {
       gst4f(it.out1, idx, it.stage == 1 ? k : in.kq + 2.0f * k);
-      const float c = (float)(it.stage == 3 ? h : 0.5 * h);
-      f4v o;
-#pragma unroll
-      for (int e = 0; e < EV; ++e) o[e] = (float)in.p.v[e] + c * k[e];
-      st_op4f<DT>(it.out0, idx, np2, o);
+      st_op4f<DT>(it.out0, idx, np2, in.xf + (float)(it.stage == 3 ? h : 0.5 * h) * k);
     }
   } else if constexpr (EPI == EPI_EULER) {
     const V4 a = widen(af);
@@ -576,6 +568,16 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
   T (*As)[A_STAGE] = reinterpret_cast<T (*)[A_STAGE]>(smem);
   T (*Bs)[B_STAGE] = reinterpret_cast<T (*)[B_STAGE]>(smem + NS * A_STAGE * sizeof(T));
 
+  // Workgroup barrier for LDS reuse.  The 16-bit epilogue's stores need not
+  // complete at it (no workgroup reads another's global writes within a
+  // launch): waiting only for LDS lets them drain behind later work, where
+  // __syncthreads would wait for every one of them.
+  auto epi_sync = [](auto lds_only_c) {
+    if constexpr (decltype(lds_only_c)::value)
+      asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else
+      __syncthreads();
+  };
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -869,7 +871,8 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
       });
     };
 
-    __syncthreads();  // the previous output tile's epilogue may still read LDS
+    // the previous output tile's epilogue may still read LDS
+    epi_sync(std::integral_constant<bool, (DT != DT_F64 && DT != DT_F32)>());
     if constexpr (RING) {
       static_for(std::make_integer_sequence<int, NS>(), [&](auto s_c) {
         constexpr int st = decltype(s_c)::value;
@@ -909,9 +912,13 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
       static_assert(CROWS * CLD * (int)sizeof(Acc) <= SMEM, "epilogue staging must fit in LDS");
       Acc* Cs = reinterpret_cast<Acc*>(smem);
       const int n_valid = it.n;
+      // ITER element groups per thread and pass, handled EG at a time
+      constexpr int ITER = CROWS * BN / EV / NT;
+      constexpr int EG = (DT == DT_F64 || DT == DT_F32) ? 1 : (ITER < 2 ? ITER : 2);
+      static_assert(CROWS * BN / EV % NT == 0 && ITER % EG == 0, "epilogue split");
 #pragma unroll
       for (int i = 0; i < RM; ++i) {
-        __syncthreads();  // K loop / previous pass readers are done with LDS
+        epi_sync(std::integral_constant<bool, (EG > 1)>());  // K loop / previous pass readers are done with LDS
 #pragma unroll
         for (int j = 0; j < RN; ++j)
 #pragma unroll
@@ -920,12 +927,7 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
             acc_pos<DT>(lane, v, r, c);
             Cs[(wr * MI + r) * CLD + wc * WN + j * MI + c] = (Acc)acc[i][j][v];
           }
-        __syncthreads();
-        // ITER element groups per thread, handled EG at a time: the loads
-        // of a batch are all issued before its first group is combined
-        constexpr int ITER = CROWS * BN / EV / NT;
-        constexpr int EG = (DT == DT_F64 || DT == DT_F32) ? 1 : (ITER < 2 ? ITER : 2);
-        static_assert(CROWS * BN / EV % NT == 0 && ITER % EG == 0, "epilogue split");
+        epi_sync(std::integral_constant<bool, (EG > 1)>());
         if constexpr (EG == 1) {
           for (int e = tid; e < CROWS * BN / EV; e += NT) {
             const int rr = (e * EV) / BN, cc = (e * EV) % BN;
@@ -937,29 +939,39 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
             const int dpos = (gr >= gc && gr < gc + EV && gr < n_valid) ? gr - gc : -1;
             epilogue4<DT, EPI>(it, (int64_t)gr * np + gc, dpos, a);
           }
-        } else
+        } else {
+          // ITER / EG rounds; the loads of round r+1 are issued before the
+          // stores of round r: loads and stores share one in-order counter,
+          // so waiting for loads issued after a store waits for that store
+          constexpr int ROUNDS = ITER / EG;
+          EpiIn in[2][EG];
+          int64_t idx[2][EG];
+          auto load_round = [&](int r, auto b_c) {
+            constexpr int b = decltype(b_c)::value;
 #pragma unroll
-        for (int g0 = 0; g0 < ITER; g0 += EG) {
-          EpiIn in[EG];
-          int64_t idx[EG];
+            for (int g = 0; g < EG; ++g) {
+              const int e = tid + (r * EG + g) * NT;
+              const int rr = (e * EV) / BN, cc = (e * EV) % BN;
+              const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
+              idx[b][g] = (int64_t)gr * np + col0 + cc;
+              in[b][g] = epi_load<DT, EPI>(it, idx[b][g]);
+            }
+          };
+          load_round(0, std::integral_constant<int, 0>());
+          static_for(std::make_integer_sequence<int, ROUNDS>(), [&](auto r_c) {
+            constexpr int r = decltype(r_c)::value;
+            if constexpr (r + 1 < ROUNDS) load_round(r + 1, std::integral_constant<int, (r + 1) & 1>());
 #pragma unroll
-          for (int g = 0; g < EG; ++g) {
-            const int e = tid + (g0 + g) * NT;
-            const int rr = (e * EV) / BN, cc = (e * EV) % BN;
-            const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
-            idx[g] = (int64_t)gr * np + col0 + cc;
-            in[g] = epi_load<DT, EPI>(it, idx[g]);
-          }
-#pragma unroll
-          for (int g = 0; g < EG; ++g) {
-            const int e = tid + (g0 + g) * NT;
-            const int rr = (e * EV) / BN, cc = (e * EV) % BN;
-            const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
-            const int gc = col0 + cc;
-            const f4v af = *(const f4v*)&Cs[rr * CLD + cc];
-            const int dpos = (gr >= gc && gr < gc + EV && gr < n_valid) ? gr - gc : -1;
-            epi_apply<DT, EPI>(it, idx[g], dpos, af, in[g]);
-          }
+            for (int g = 0; g < EG; ++g) {
+              const int e = tid + (r * EG + g) * NT;
+              const int rr = (e * EV) / BN, cc = (e * EV) % BN;
+              const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
+              const int gc = col0 + cc;
+              const f4v af = *(const f4v*)&Cs[rr * CLD + cc];
+              const int dpos = (gr >= gc && gr < gc + EV && gr < n_valid) ? gr - gc : -1;
+              epi_apply<DT, EPI>(it, idx[r & 1][g], dpos, af, in[r & 1][g]);
+            }
+          });
         }
       }
     }
