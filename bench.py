@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--max-iter", type=int, default=64)
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serial", action="store_true",
+                    help="also time the serial fine solve after the benchmark (off by default: its one-product "
+                         "launches of the same kernel would blend into a profile's per-kernel average)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -130,6 +133,26 @@ def main():
         log("step %d: iters %d, increment %.3e, status %d" % (k, s["iters"], s["increment"], st))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+
+    # outside the timed region: the serial fine solve that the parareal
+    # iteration converges to (N*S RK4 steps from X0 = I on one GPU), for the
+    # comparison a single GPU can show; parareal pays off when slices run on
+    # separate GPUs
+    serial = None
+    if args.serial:
+        log("serial fine solve: %d RK4 steps" % (N * S))
+        X0 = torch.eye(n, dtype=torch.float64, device="cuda")
+        Xs = torch.empty_like(X0)
+        fm.fm_fine_propagate(h, 1.0 / (N * S), 0.0, 1, [X0], [Xs], stream=stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fm.fm_fine_propagate(h, 1.0, 0.0, N * S, [X0], [Xs], stream=stream)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t
+        serial = {"seconds": ts, "rk4_steps": N * S, "tflops": N * S * 16.0 * n ** 3 / ts / 1e12,
+                  "rel_diff_vs_parareal": float(torch.linalg.norm(out - Xs) / torch.linalg.norm(Xs))}
+        log("serial fine: %.2f s (parareal solve %.2f s), rel diff %.2e" % (ts, elapsed / args.steps,
+                                                                           serial["rel_diff_vs_parareal"]))
     fm.fm_destroy(h)
 
     s = stats[-1]
@@ -177,6 +200,7 @@ def main():
                      "kernel": "gemm_kernel RK4-epilogue (fine propagator), avg of %d launches, %.3e flop/launch"
                                % (s["fine_launches"], flops_per_launch)},
         "cpu_baseline": cpu,
+        "serial_fine": serial,
     }
     print(json.dumps(res), flush=True)
 

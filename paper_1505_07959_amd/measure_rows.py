@@ -24,6 +24,17 @@ def _timed(fn):
     return out, time.perf_counter() - t
 
 
+def _serial_fine(flow, ns, T, steps):
+    """GPU wall time of the serial fine solve the parareal iteration converges
+    to: all N*S RK4 steps from X0 = I over [0, T] for every problem of the
+    flow, in one fm_fine_propagate call (after a one-step warm-up)."""
+    X0 = [torch.eye(n, dtype=torch.float64, device="cuda") for n in ns]
+    Xs = [torch.empty((n, n), dtype=torch.float64, device="cuda") for n in ns]
+    fm.fm_fine_propagate(flow, T / steps, 0.0, 1, X0, Xs)
+    _, sec = _timed(lambda: fm.fm_fine_propagate(flow, T, 0.0, steps, X0, Xs))
+    return sec, Xs
+
+
 def _solve(kind, A, prm, dtype="f64", options="timing=1"):
     n = A.shape[0]
     h = fm.fm_flow_create([(kind, A)], dtype, options)
@@ -117,8 +128,19 @@ def batched(count=512, tol=1e-3):
         (st, stats), sec = _timed(lambda: fm.fm_parareal_solve(flow, None, outs, prm))
     finally:
         fm.fm_destroy(flow)
+    # serial fine solves of the same problems (one flow per kind: the two
+    # halves end at different T)
+    serial = 0.0
+    for kind, T in ((fm.FM_FLOW_INV_HOMOTOPY, 1.0), (fm.FM_FLOW_SQRT_STEADY, 20.0)):
+        sub = [c for c in cases if c[0] == kind]
+        f2 = fm.fm_flow_create([(kind, torch.from_numpy(A).cuda()) for k, T2, A, Q, lam in sub], "bf16")
+        try:
+            serial += _serial_fine(f2, [c[2].shape[0] for c in sub], T, 64 * 8)[0]
+        finally:
+            fm.fm_destroy(f2)
     its = [s["iters"] for s in stats]
-    return {"workload": "batched%d_bf16_N64_S8_tol%g_refined" % (count, tol), "seconds": sec, "solves_per_s": count / sec,
+    return {"workload": "batched%d_bf16_N64_S8_tol%g_refined" % (count, tol), "seconds": sec,
+            "serial_fine_seconds": serial, "solves_per_s": count / sec,
             "iterations_max": max(its), "iterations_mean": float(np.mean(its)),
             "refine_steps_max": max(s["refine_steps"] for s in stats),
             "residual_max": max(s["residual"] for s in stats)}
@@ -142,14 +164,16 @@ def learned_vs_euler(kind=fm.FM_FLOW_INV_HOMOTOPY):
     res = []
     try:
         fm.fm_parareal_solve(flow, None, [out], [{"T": T, "N": N, "fine_steps": S, "max_iter": 1, "tol": 0.0}])
+        serial, Xs = _serial_fine(flow, [n], T, N * S)
         for name, coarse in (("euler", fm.FM_COARSE_EULER), ("learned", fm.FM_COARSE_LEARNED)):
             prm = {"T": T, "N": N, "fine_steps": S, "max_iter": N, "tol": tol, "coarse": coarse}
             (st, stats), sec = _timed(lambda: fm.fm_parareal_solve(flow, None, [out], [prm]))
             s = stats[0]
             res.append({"workload": "%s_n%d_N%d_S%d_%s_tol%g_%s" % ("homotopy" if kind == 1 else "steady", n, N, S,
                                                                     dt, tol, name),
-                        "iterations": s["iters"], "seconds": sec, "restarts": s["learned_restarts"],
-                        "status": st})
+                        "iterations": s["iters"], "seconds": sec, "serial_fine_seconds": serial,
+                        "rel_diff_vs_serial_fine": float(torch.linalg.norm(out - Xs[0]) / torch.linalg.norm(Xs[0])),
+                        "restarts": s["learned_restarts"], "status": st})
     finally:
         fm.fm_destroy(flow)
     return res
