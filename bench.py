@@ -71,10 +71,23 @@ def cpu_baseline(A, n, fine_steps_total, coarse_steps_total, sample_steps):
     t_step = (time.perf_counter() - t0) / sample_steps
     # one Euler step = 2 of the 8 products of an RK4 step
     t_solve = t_step * (fine_steps_total + 0.25 * coarse_steps_total)
+    # the same on one core: one of the eight products of an RK4 step, timed
+    # with the BLAS limited to one thread and scaled by 8
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            alg.mul(X, M)
+            t_prod = time.perf_counter() - t1
+        one = 1.0 / (8.0 * t_prod * (fine_steps_total + 0.25 * coarse_steps_total))
+    except Exception:
+        pass
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+            "value_one_core": one,
             "sample": "%d RK4 steps of the n=%d matrix oracle (numpy FP64, %.2f s/step), scaled by the %d RK4 "
-                      "and %d Euler steps of one GPU solve" % (sample_steps, n, t_step, fine_steps_total,
-                                                              coarse_steps_total)}
+                      "and %d Euler steps of one GPU solve; one core: one product of an RK4 step at one BLAS "
+                      "thread, scaled by 8" % (sample_steps, n, t_step, fine_steps_total, coarse_steps_total)}
 
 
 def main():
@@ -189,8 +202,10 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": "inverse homotopy dX/dt=X(I-A)X, n=%d SPD lam~U[0.05,4] seed 2, N=%d slices, "
-                               "RK4 %d steps/slice, Euler 1 step/slice, %s MFMA products, FP64 state+correction, "
-                               "stop at increment <= %g" % (n, N, S, args.dtype, args.tol),
+                               "RK4 %d steps/slice, Euler 1 step/slice, %s MFMA products, %s, FP64 correction, "
+                               "stop at increment <= %g" % (n, N, S, args.dtype,
+                                                            "FP32 fine-solve state" if args.dtype in ("bf16", "f16", "bf16x3")
+                                                            else "FP64 state", args.tol),
                    "n": n, "slices": N, "fine_steps": S, "coarse_steps": 1, "tol": args.tol,
                    "iterations": iters, "converged": converged,
                    "fine_tflops_whole_solve": total_fine_flops / (elapsed / args.steps) / 1e12},

@@ -359,7 +359,7 @@ __device__ __forceinline__ void add_diag(V4& v, int dpos, double d) {
 }
 
 struct EpiIn {
-  V4 p, q, r;  // FP64: state (RK4/Euler), POLYP/POLYX inputs, E of an FP64 output
+  V4 p, q, r;  // FP64: Euler state, POLYP/POLYX inputs, E of an FP64 output
   f4v kq, er;  // FP32: RK4 stage accumulator, E
   f4v xf;      // FP32 RK4 state (F_X_F32)
 };
