@@ -203,7 +203,6 @@ fm_status Flow::ensure_hredu(size_t count) {
 }
 
 // ------------------------------------------------------------------ configs
-static int pad_order(int n) { return (n + 63) / 64 * 64; }
 
 static int default_bk(int dt) { return dt == DT_F64 ? 16 : (dt == DT_F32 ? 32 : 64); }  // BF16X3: 64
 
@@ -222,9 +221,10 @@ static GemmCfg default_cfg(int d, int np) {
 // plain product and the product with the fused stage update).  All configurations sum over k in
 // the same order, so the choice changes speed only, never results.  Choices are
 // kept for the process and, with autotune_cache=<file>, across processes
-// (lines "device dtype np bm bk").
+// (lines "device dtype np bm bk ms", ms = trial time per product).
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int>, GemmCfg> g_tune;
+static std::map<std::tuple<int, int, int>, double> g_tune_ms;
 static std::map<std::string, bool> g_tune_loaded;
 
 static void tune_load(const std::string& path) {
@@ -233,17 +233,21 @@ static void tune_load(const std::string& path) {
   FILE* f = fopen(path.c_str(), "r");
   if (!f) return;
   int dev, d, np, bm, bk;
-  while (fscanf(f, "%d %d %d %d %d", &dev, &d, &np, &bm, &bk) == 5)
+  double ms;
+  while (fscanf(f, "%d %d %d %d %d %lf", &dev, &d, &np, &bm, &bk, &ms) == 6)
     for (const GemmCfg& c : gemm_configs(d))
-      if (c.bm == bm && c.bk == bk && np % bm == 0 && np % bk == 0) g_tune[{dev, d, np}] = c;
+      if (c.bm == bm && c.bk == bk && np % bm == 0 && np % bk == 0) {
+        g_tune[{dev, d, np}] = c;
+        g_tune_ms[{dev, d, np}] = ms;
+      }
   fclose(f);
 }
 
-static void tune_store(const std::string& path, int dev, int d, int np, const GemmCfg& c) {
+static void tune_store(const std::string& path, int dev, int d, int np, const GemmCfg& c, double ms) {
   if (path.empty()) return;
   FILE* f = fopen(path.c_str(), "a");
   if (!f) return;
-  fprintf(f, "%d %d %d %d %d\n", dev, d, np, c.bm, c.bk);
+  fprintf(f, "%d %d %d %d %d %.6g\n", dev, d, np, c.bm, c.bk, ms);
   fclose(f);
 }
 
@@ -296,6 +300,42 @@ static double time_cfg(const GemmCfg& c, int np, int nb, void* A, void* B, void*
   return best;
 }
 
+// Padded order of a problem of order n: the multiples of 64, 128 and 256 at
+// or above n (one to three distinct orders), each with its tuned tile; the
+// one with the shortest trial time per product wins.  Zero padding leaves
+// the leading n x n block unchanged and every tile shape sums over k in the
+// same order, so the choice changes speed only.  A larger order can win
+// because it admits wider tiles (n = 448: 448 takes 64-wide tiles only, 512
+// the 256-wide ring).  Without autotuning, or with a fixed tile, the multiple
+// of 64.
+int Flow::pick_order(int d, int n) {
+  const int p64 = (n + 63) / 64 * 64;
+  if (!autotune || force_bm) return p64;
+  std::vector<int> orders;
+  for (int m : {64, 128, 256}) {
+    const int o = (n + m - 1) / m * m;
+    if (std::find(orders.begin(), orders.end(), o) == orders.end()) orders.push_back(o);
+  }
+  if (orders.size() == 1) return p64;
+  int best = p64;
+  double best_ms = 1e30;
+  for (int o : orders) {
+    (void)pick_cfg(d, o);
+    double ms = 1e30;
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      auto it = g_tune_ms.find(std::make_tuple(device, d, o));
+      if (it != g_tune_ms.end()) ms = it->second;
+    }
+    if (verbose) fprintf(stderr, "[fm] order n=%d np=%d: %.3g ms per product\n", n, o, ms);
+    if (ms < 0.95 * best_ms) {  // a larger order must be clearly faster
+      best_ms = ms;
+      best = o;
+    }
+  }
+  return best;
+}
+
 GemmCfg Flow::pick_cfg(int d, int np) {
   const GemmCfg def = default_cfg(d, np);
   if (force_bm && d == dt) {
@@ -315,7 +355,7 @@ GemmCfg Flow::pick_cfg(int d, int np) {
   std::vector<GemmCfg> cand;
   for (const GemmCfg& c : gemm_configs(d))
     if (np % c.bm == 0 && np % c.bk == 0) cand.push_back(c);
-  if (cand.size() <= 1) return def;
+  if (cand.empty()) return def;
   // A batch of products of this order large enough that the largest
   // candidate tile fills the GPU too (>= 1024 tiles): a solve's fine phase
   // launches slices x problems products at once, and a batch that only the
@@ -336,6 +376,7 @@ GemmCfg Flow::pick_cfg(int d, int np) {
   hipStream_t st = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   GemmCfg best_c = def;
+  double best = 1e30;
   bool ok = hipMalloc(&A, np2 * esz) == hipSuccess && hipMalloc(&B, np2 * esz) == hipSuccess &&
             hipMalloc(&C, np2 * esz * 2 * nb) == hipSuccess && hipMalloc(&Kacc, np2 * asz * nb) == hipSuccess &&
             hipMalloc((void**)&Xs, np2 * 8 * nb) == hipSuccess &&
@@ -346,16 +387,30 @@ GemmCfg Flow::pick_cfg(int d, int np) {
             fill_pattern(B, d, (int64_t)np2, st) == hipSuccess &&
             fill_pattern(Xs, DT_F64, (int64_t)np2 * nb, st) == hipSuccess;
   if (ok) {
-    double best = 1e30;
-    for (const GemmCfg& c : cand) {
-      const double ms = time_cfg(c, np, nb, A, B, C, Xs, Kacc, di, dts, st, e0, e1);
-      if (verbose) fprintf(stderr, "[fm] autotune dt=%d np=%d bm=%d bk=%d: %.3f ms\n", d, np, c.bm, c.bk, ms);
-      if (ms < best) {
-        best = ms;
-        best_c = c;
-      }
+    std::vector<double> t(cand.size());
+    for (size_t j = 0; j < cand.size(); ++j) {
+      const GemmCfg& c = cand[j];
+      t[j] = time_cfg(c, np, nb, A, B, C, Xs, Kacc, di, dts, st, e0, e1);
+      if (verbose) fprintf(stderr, "[fm] autotune dt=%d np=%d bm=%d bk=%d: %.3f ms\n", d, np, c.bm, c.bk, t[j]);
+      best = std::min(best, t[j]);
     }
-    if (best >= 1e29) best_c = def;
+    // Within 5 % of the fastest, the narrowest tile wins: it gives launches
+    // of few products (a fine solve of one problem) more workgroups, where
+    // the trial batch, which fills the GPU with any tile, cannot tell them
+    // apart.
+    if (best < 1e29) {
+      int bm = 1 << 30;
+      double chosen = best;
+      for (size_t j = 0; j < cand.size(); ++j)
+        if (t[j] <= 1.05 * best && cand[j].bm < bm) {
+          bm = cand[j].bm;
+          best_c = cand[j];
+          chosen = t[j];
+        }
+      best = chosen;
+    } else {
+      best_c = def;
+    }
   }
   if (st) (void)hipStreamSynchronize(st);
   if (A) (void)hipFree(A);
@@ -370,7 +425,8 @@ GemmCfg Flow::pick_cfg(int d, int np) {
   if (st) (void)hipStreamDestroy(st);
   (void)hipGetLastError();
   g_tune[key] = best_c;
-  tune_store(autotune_cache, device, d, np, best_c);
+  g_tune_ms[key] = best < 1e29 ? best / nb : 1e30;
+  tune_store(autotune_cache, device, d, np, best_c, g_tune_ms[key]);
   if (verbose) fprintf(stderr, "[fm] autotune dt=%d np=%d -> bm=%d bk=%d\n", d, np, best_c.bm, best_c.bk);
   return best_c;
 }
@@ -418,7 +474,7 @@ fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char*
     Inst& in = inst[i];
     in.kind = p[i].kind;
     in.n = (int)p[i].n;
-    in.np = pad_order(in.n);
+    in.np = pick_order(dt, in.n);
     in.cfg = pick_cfg(dt, in.np);
     in.cfg64 = pick_cfg(DT_F64, in.np);
     const size_t np2 = (size_t)in.np * in.np;

@@ -192,6 +192,7 @@ struct Flow {
 
   fm_status load_model(const std::string& path);
   GemmCfg pick_cfg(int dt, int np);
+  int pick_order(int dt, int n);
 };
 
 }  // namespace fm
