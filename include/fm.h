@@ -167,15 +167,17 @@ typedef struct {
  * dtype copies); allocates the parareal workspace lazily in the first solve.
  * options: NULL or "key=value;key=value": coarse_model=<path> loads learned
  * coarse weights (file written by the training script), autotune=0|1 (default
- * 1: time candidate tile shapes on first use), autotune_cache=<path>,
+ * 1: on first use of an order, time the candidate tile shapes and the
+ * candidate padded orders, the multiples of 64, 128 and 256 at or above n;
+ * 0: the multiple of 64 and a default tile), autotune_cache=<path>,
  * timing=0|1 (default 0: fill the timing fields of fm_stats), verbose=0|1
  * (one stderr line per parareal iteration and per tile choice),
  * tile=<bm>x<bk> (fixed product tile instead of the autotuned one, for the
  * products in the flow's dtype; FM_ERR_INVALID unless compiled for that
  * dtype: FP64 128x16, 128x32, 64x16, 64x32; FP32 128x32, 128x16, 64x32;
  * BF16 and FP16 128x64, 128x32, 256x32, 256x64, 64x64; split BF16 128x64,
- * 256x32, 64x64; ignored for a problem whose padded order it does not
- * divide), graph=0|1 (default 1: the launches of one RK4 step of a
+ * 256x32, 64x64; problems are then padded to a multiple of 64, and the tile
+ * is ignored for a problem whose padded order it does not divide), graph=0|1 (default 1: the launches of one RK4 step of a
  * fine phase are captured in a hipGraph and replayed for every step; off
  * while timing=1).  Tile shapes and graphs never change results.
  * out: host; receives the handle.  Returns FM_ERR_INVALID for batch < 1,
