@@ -177,9 +177,10 @@ typedef struct {
  * dtype: FP64 128x16, 128x32, 64x16, 64x32; FP32 128x32, 128x16, 64x32;
  * BF16 and FP16 128x64, 128x32, 256x32, 256x64, 64x64; split BF16 128x64,
  * 256x32, 64x64; problems are then padded to a multiple of 64, and the tile
- * is ignored for a problem whose padded order it does not divide), graph=0|1 (default 1: the launches of one RK4 step of a
- * fine phase are captured in a hipGraph and replayed for every step; off
- * while timing=1).  Tile shapes and graphs never change results.
+ * is ignored for a problem whose padded order it does not divide),
+ * graph=0|1 (default 1: the launches of one RK4 step of a fine phase are
+ * captured in a hipGraph and replayed for every step; off while timing=1).
+ * Tile shapes, padded orders and graphs never change results.
  * out: host; receives the handle.  Returns FM_ERR_INVALID for batch < 1,
  * n out of range, lda < n, an unknown kind/dtype or a NULL A.
  */
