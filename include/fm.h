@@ -180,7 +180,8 @@ typedef struct {
  * is ignored for a problem whose padded order it does not divide),
  * graph=0|1 (default 1: the launches of one RK4 step of a fine phase are
  * captured in a hipGraph and replayed for every step; off while timing=1).
- * Tile shapes, padded orders and graphs never change results.
+ * Tile shapes and graphs never change results; the padded order can change
+ * them at rounding level only (the summation order of norms and dot products).
  * out: host; receives the handle.  Returns FM_ERR_INVALID for batch < 1,
  * n out of range, lda < n, an unknown kind/dtype or a NULL A.
  */

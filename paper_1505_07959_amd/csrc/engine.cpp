@@ -303,8 +303,8 @@ static double time_cfg(const GemmCfg& c, int np, int nb, void* A, void* B, void*
 // Padded order of a problem of order n: the multiples of 64, 128 and 256 at
 // or above n (one to three distinct orders), each with its tuned tile; the
 // one with the shortest trial time per product wins.  Zero padding leaves
-// the leading n x n block unchanged and every tile shape sums over k in the
-// same order, so the choice changes speed only.  A larger order can win
+// the leading n x n block of every product unchanged; only the summation
+// order of norms and dot products over the padded matrices depends on it.  A larger order can win
 // because it admits wider tiles (n = 448: 448 takes 64-wide tiles only, 512
 // the 256-wide ring).  Without autotuning, or with a fixed tile, the multiple
 // of 64.
