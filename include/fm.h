@@ -169,7 +169,8 @@ typedef struct {
  * coarse weights (file written by the training script), autotune=0|1 (default
  * 1: on first use of an order, time the candidate tile shapes and the
  * candidate padded orders, the multiples of 64, 128 and 256 at or above n;
- * 0: the multiple of 64 and a default tile), autotune_cache=<path>,
+ * 0: the multiple of 64 and a default tile), pad=64|128|256 (fixed padding
+ * multiple instead of the tuned one), autotune_cache=<path>,
  * timing=0|1 (default 0: fill the timing fields of fm_stats), verbose=0|1
  * (one stderr line per parareal iteration and per tile choice),
  * tile=<bm>x<bk> (fixed product tile instead of the autotuned one, for the

@@ -307,8 +307,9 @@ static double time_cfg(const GemmCfg& c, int np, int nb, void* A, void* B, void*
 // order of norms and dot products over the padded matrices depends on it.  A larger order can win
 // because it admits wider tiles (n = 448: 448 takes 64-wide tiles only, 512
 // the 256-wide ring).  Without autotuning, or with a fixed tile, the multiple
-// of 64.
+// of 64; with option pad=<m>, the multiple of m.
 int Flow::pick_order(int d, int n) {
+  if (force_pad) return (n + force_pad - 1) / force_pad * force_pad;
   const int p64 = (n + 63) / 64 * 64;
   if (!autotune || force_bm) return p64;
   std::vector<int> orders;
@@ -458,6 +459,13 @@ fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char*
   if (kv.count("verbose")) verbose = kv["verbose"] != "0";
   if (kv.count("graph")) use_graph = kv["graph"] != "0";
   if (use_graph) FM_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+  if (kv.count("pad")) {
+    force_pad = atoi(kv["pad"].c_str());
+    if (force_pad != 64 && force_pad != 128 && force_pad != 256) {
+      set_error("option pad must be 64, 128 or 256");
+      return FM_ERR_INVALID;
+    }
+  }
   if (kv.count("tile")) {
     bool known = sscanf(kv["tile"].c_str(), "%dx%d", &force_bm, &force_bk) == 2;
     bool found = false;

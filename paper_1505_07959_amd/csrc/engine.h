@@ -118,6 +118,7 @@ struct Flow {
   Model model;
   bool autotune = true;
   int force_bm = 0, force_bk = 0;  // option tile=<bm>x<bk>: fixed product tile (flow dtype)
+  int force_pad = 0;                // option pad=64|128|256: fixed padding multiple
   std::string autotune_cache;
   Ring ring;
   Arena work;      // parareal workspace
