@@ -121,3 +121,25 @@ def test_unknown_padding_is_rejected():
     with pytest.raises(fm.FmError) as ei:
         fm.fm_flow_create([(HOMOTOPY, dev(A))], "f64", "pad=96")
     assert ei.value.status == fm.FM_ERR_INVALID
+
+
+@pytest.mark.parametrize("dtype", sorted(TILES))
+def test_every_tile_gives_bitwise_identical_products(dtype):
+    """All compiled tiles of a product type walk the same k-chunks in the
+    same order, so their fine propagations agree bit for bit (the autotuner
+    changes speed only)."""
+    from paper_1505_07959_amd import fm
+    import numpy as np
+    say("tile bitwise invariance dtype=%s n=%d" % (dtype, N))
+    A, X0 = _case(11)
+    outs = []
+    for bm, bk in TILES[dtype]:
+        h = fm.fm_flow_create([(INV_LINEAR, dev(A))], dtype, "tile=%dx%d" % (bm, bk))
+        try:
+            out = empty(N)
+            fm.fm_fine_propagate(h, 0.3, 0.1, 3, [dev(X0)], [out])
+            outs.append(host(out))
+        finally:
+            fm.fm_destroy(h)
+    for (bm, bk), o in zip(TILES[dtype][1:], outs[1:]):
+        assert np.array_equal(outs[0], o), "tile %dx%d differs from %dx%d" % (bm, bk, *TILES[dtype][0])
