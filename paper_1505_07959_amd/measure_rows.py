@@ -146,17 +146,19 @@ def batched(count=512, tol=1e-3):
             "residual_max": max(s["residual"] for s in stats)}
 
 
-def learned_vs_euler(kind=fm.FM_FLOW_INV_HOMOTOPY):
+def learned_vs_euler(kind=fm.FM_FLOW_INV_HOMOTOPY, dtype=None, tol=None):
     """Learned vs Euler coarse step: the n = 2048 homotopy (N = 128, S = 8,
     FP64, to 1e-8) or the n = 8192 X - XAX flow (N = 32, S = 16, T = 30,
     FP16 products, to 1e-3), each after one warm-up solve of the flow."""
     from paper_1505_07959_amd import eval_coarse
     if kind == fm.FM_FLOW_INV_HOMOTOPY:
-        n, N, S, T, dt, tol = 2048, 128, 8, 1.0, "f64", 1e-8
+        n, N, S, T, dt, tl = 2048, 128, 8, 1.0, "f64", 1e-8
         A = inputs.learned_eval_problem(n)[0]
     else:
-        n, N, S, T, dt, tol = 8192, 32, 16, 30.0, "f16", 1e-3
+        n, N, S, T, dt, tl = 8192, 32, 16, 30.0, "f16", 1e-3
         A = inputs.steady_problem(n)[0]
+    dt = dtype or dt
+    tol = tol or tl
     Ad = torch.from_numpy(A).cuda()
     model = eval_coarse.DEFAULT_MODEL[kind]
     flow = fm.fm_flow_create([(kind, Ad)], dt, "coarse_model=%s" % model)
@@ -182,6 +184,7 @@ def learned_vs_euler(kind=fm.FM_FLOW_INV_HOMOTOPY):
 ROWS = {"example1": example1, "exp": exp_variants, "aima": aima, "cos": cosine, "batched": batched,
         "batched_tol1e-2": lambda: batched(tol=1e-2),
         "learned": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY),
+        "learned_f32": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY, "f32", 1e-6),
         "learned_steady": lambda: learned_vs_euler(fm.FM_FLOW_INV_STEADY)}
 
 
