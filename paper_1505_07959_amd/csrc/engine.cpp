@@ -1952,8 +1952,6 @@ fm_status Flow::refine(const std::vector<int>& which, std::vector<double*>& X, c
   std::vector<double*> R(batch, nullptr), X2(batch, nullptr), H(batch, nullptr), r(batch, nullptr),
       p(batch, nullptr), Ap(batch, nullptr), T(batch, nullptr);
   double *sc = nullptr, *dpart = nullptr;
-  bool any_sqrt = false;
-  for (int i : which) any_sqrt |= inst[i].kind == FM_FLOW_SQRT_STEADY;
   for (int pass = 0; pass < 2; ++pass) {
     prop.measuring = (pass == 0);
     prop.used = 0;

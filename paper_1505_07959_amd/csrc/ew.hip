@@ -322,7 +322,7 @@ __global__ void k_norm_inf(const double* __restrict__ a, int64_t n, int64_t ld, 
   sh[threadIdx.x] = m;
   __syncthreads();
   for (int s = EW_THREADS / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = sh[0];

@@ -483,7 +483,6 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
   using TR = Tr<DT>;
   using T = typename TR::T;
   using G16 = typename TR::G16;
-  using LV = typename TR::LV;
   using AccV = typename TR::AccV;
   using FV = typename TR::FV;
   constexpr int MI = TR::MI, V = TR::V, NACC = TR::NACC;
