@@ -97,6 +97,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--dtype", default="f64", choices=["f32", "f64", "bf16", "f16", "bf16x3"])
     ap.add_argument("--tile", default=None, help="fixed product tile <bm>x<bk> instead of the autotuned one")
+    ap.add_argument("--coarse-f64", action="store_true", help="coarse-step products in FP64 (FP32/16-bit runs)")
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--slices", type=int, default=64)
     ap.add_argument("--fine-steps", type=int, default=16)
@@ -125,7 +126,7 @@ def main():
     out = torch.empty((n, n), dtype=torch.float64, device="cuda")
     prm = {"T": 1.0, "N": N, "coarse_steps": 1, "fine_steps": S, "max_iter": args.max_iter, "tol": args.tol,
            "coarse": fm.FM_COARSE_EULER, "max_refine": 0}
-    opts = "timing=1;verbose=1" + (";tile=" + args.tile if args.tile else "")
+    opts = "timing=1;verbose=1" + (";tile=" + args.tile if args.tile else "") + (";coarse_f64=1" if args.coarse_f64 else "")
     h = fm.fm_flow_create([(fm.FM_FLOW_INV_HOMOTOPY, Ad)], args.dtype, opts)
     stream = torch.cuda.current_stream()
 

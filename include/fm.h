@@ -170,7 +170,10 @@ typedef struct {
  * 1: on first use of an order, time the candidate tile shapes and the
  * candidate padded orders, the multiples of 64, 128 and 256 at or above n;
  * 0: the multiple of 64 and a default tile), pad=64|128|256 (fixed padding
- * multiple instead of the tuned one), autotune_cache=<path>,
+ * multiple instead of the tuned one), coarse_f64=0|1 (default 0: coarse-step
+ * products, Euler or learned, in FP64 for an FP32 or 16-bit flow, so that the
+ * coarse step's own rounding does not floor the parareal increment),
+ * autotune_cache=<path>,
  * timing=0|1 (default 0: fill the timing fields of fm_stats), verbose=0|1
  * (one stderr line per parareal iteration and per tile choice),
  * tile=<bm>x<bk> (fixed product tile instead of the autotuned one, for the

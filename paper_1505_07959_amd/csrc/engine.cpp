@@ -182,6 +182,16 @@ fm_status Flow::ensure_part(size_t count) {
   part_cap = count;
   return FM_OK;
 }
+// FP64 copy of the first product's right operand (A - I for the homotopy,
+// else A), made once per problem.
+fm_status Flow::ensure_b64(int i, hipStream_t st) {
+  if (inst[i].B64) return FM_OK;
+  FM_HIP(hipMalloc((void**)&inst[i].B64, (size_t)inst[i].np * inst[i].np * 8));
+  FM_HIP(convert_f64(inst[i].B64, DT_F64, inst[i].A64, inst[i].kind == FM_FLOW_INV_HOMOTOPY ? -1.0 : 0.0,
+                     inst[i].n, inst[i].np, st));
+  return FM_OK;
+}
+
 // Growing the buffer frees the old one: hipFree waits for the device, so no
 // launch still reads it.
 fm_status Flow::ensure_x32(size_t count) {
@@ -459,6 +469,7 @@ fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char*
   if (kv.count("verbose")) verbose = kv["verbose"] != "0";
   if (kv.count("graph")) use_graph = kv["graph"] != "0";
   if (use_graph) FM_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+  if (kv.count("coarse_f64")) coarse64 = kv["coarse_f64"] != "0" && dt != DT_F64;
   if (kv.count("pad")) {
     force_pad = atoi(kv["pad"].c_str());
     if (force_pad != 64 && force_pad != 128 && force_pad != 256) {
@@ -491,6 +502,7 @@ fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char*
     if (in.kind != FM_FLOW_SQRT_STEADY) {
       FM_HIP(hipMalloc(&in.Bop, np2 * dt_size(dt)));
       FM_HIP(convert_f64(in.Bop, dt, in.A64, in.kind == FM_FLOW_INV_HOMOTOPY ? -1.0 : 0.0, in.n, in.np, st));
+      if (coarse64) FM_TRY(ensure_b64(i, st));
     }
   }
   if (kv.count("coarse_model")) FM_TRY(load_model(kv["coarse_model"]));
@@ -541,7 +553,8 @@ static bool two_products(int kind) { return kind == FM_FLOW_INV_HOMOTOPY || kind
 
 // The stage-field product of item g (reading stage operand y, and P = B y
 // for the two-product flows): k = s0 (a b) + s1 E + s3 I per flow kind.
-static void field_item(GItem& g, const Inst& in, void* y, void* p) {
+static void field_item(GItem& g, const Inst& in, void* y, void* p, void* bop = nullptr) {
+  if (!bop) bop = in.Bop;
   switch (in.kind) {
     case FM_FLOW_INV_HOMOTOPY:  // k = -Y (M Y)
       g.a = y;
@@ -566,13 +579,13 @@ static void field_item(GItem& g, const Inst& in, void* y, void* p) {
       g.flags = F_E_F64;
       break;
     case FM_FLOW_EXP:  // k = A Y
-      g.a = in.Bop;
+      g.a = bop;
       g.b = y;
       g.s[0] = 1.0;
       g.flags = F_E_NONE;
       break;
     default:  // FM_FLOW_INV_LINEAR: k = I - A Y
-      g.a = in.Bop;
+      g.a = bop;
       g.b = y;
       g.s[0] = -1.0;
       g.s[3] = 1.0;
@@ -800,6 +813,9 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
 // slot.xin to slot.xout.  Operands ping-pong between y0 and y1.
 fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipStream_t st) {
   if (slots.empty() || steps <= 0) return FM_OK;
+  // option coarse_f64: operands, products and B in FP64 (B64 is made at
+  // flow creation)
+  auto cbop = [&](const Inst& in) -> void* { return coarse64 ? (void*)in.B64 : in.Bop; };
   {
     std::vector<PrepItem> prep;
     for (const CoarseSlot& sl : slots) {
@@ -815,7 +831,7 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
     }
     void* d = nullptr;
     FM_TRY(push(prep.data(), prep.size() * sizeof(PrepItem), &d, st));
-    FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), dt, nullptr, st));
+    FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), coarse64 ? DT_F64 : dt, nullptr, st));
   }
   for (int j = 0; j < steps; ++j) {
     std::vector<GItem> l1, l2, l3, l4;
@@ -828,7 +844,7 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
       if (!sl.learned) {
         if (two_products(in.kind)) {
           GItem g = blank_item(in, sl.inst);
-          g.a = in.Bop;
+          g.a = cbop(in);
           g.b = yin;
           g.out0 = sl.p;
           g.flags = F_E_NONE;
@@ -837,7 +853,7 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
           i1.push_back(sl.inst);
         }
         GItem g = blank_item(in, sl.inst);
-        field_item(g, in, yin, sl.p);
+        field_item(g, in, yin, sl.p, cbop(in));
         g.out0 = yout;
         g.out1 = sl.xout;
         g.x = const_cast<double*>(x);
@@ -849,7 +865,7 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
         // X+ = Y P + c4 I + c5 K + c6 K2 + c7 K3
         const double* c = sl.coef + 8 * j;
         GItem g = blank_item(in, sl.inst);
-        g.a = in.Bop;
+        g.a = cbop(in);
         g.b = yin;
         g.out0 = sl.k1;
         g.flags = F_E_NONE;
@@ -896,13 +912,13 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
       return FM_ERR_INVALID;
     }
     if (!any_learned) {
-      FM_TRY(gemm_groups(EPI_AFFINE, l1, i1, false, st));
-      FM_TRY(gemm_groups(EPI_EULER, l2, i2, false, st));
+      FM_TRY(gemm_groups(EPI_AFFINE, l1, i1, coarse64, st));
+      FM_TRY(gemm_groups(EPI_EULER, l2, i2, coarse64, st));
     } else {
-      FM_TRY(gemm_groups(EPI_AFFINE, l1, i1, false, st));
-      FM_TRY(gemm_groups(EPI_AFFINE, l2, i2, false, st));
-      FM_TRY(gemm_groups(EPI_POLYP, l3, i3, false, st));
-      FM_TRY(gemm_groups(EPI_POLYX, l4, i4, false, st));
+      FM_TRY(gemm_groups(EPI_AFFINE, l1, i1, coarse64, st));
+      FM_TRY(gemm_groups(EPI_AFFINE, l2, i2, coarse64, st));
+      FM_TRY(gemm_groups(EPI_POLYP, l3, i3, coarse64, st));
+      FM_TRY(gemm_groups(EPI_POLYX, l4, i4, coarse64, st));
     }
   }
   return FM_OK;
@@ -975,7 +991,7 @@ fm_status Flow::coarse_propagate(double t1, double t0, int steps, int coarse, co
     prop.used = 0;
     for (int i = 0; i < batch; ++i) {
       const size_t np2 = (size_t)inst[i].np * inst[i].np;
-      const size_t e = dt_size(dt);
+      const size_t e = coarse_esz();
       CoarseSlot& s = slots[i];
       s.inst = i;
       double* xi = (double*)prop.take(np2 * 8);
@@ -1029,7 +1045,9 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
     }
     return worst;
   }
-  const size_t e = dt_size(dt), ea = acc_size(dt);
+  // operand scratch that the coarse step shares (its own, and the slices'
+  // buffers that the learned candidates borrow) holds FP64 with coarse_f64
+  const size_t e = std::max<size_t>(dt_size(dt), coarse_esz()), ea = std::max<size_t>(acc_size(dt), coarse_esz());
   int Nmax = 0;
   for (int i = 0; i < batch; ++i) Nmax = std::max(Nmax, prm[i].N);
   bool any_learned = false;
@@ -1519,7 +1537,9 @@ fm_status Flow::solve_modified(int i, const double* X0, double* Xout, const fm_p
   const bool affine = in.kind == FM_FLOW_INV_LINEAR;
   const size_t np2 = (size_t)in.np * in.np;
   const int64_t cnt = (int64_t)np2;
-  const size_t e = dt_size(dt), ea = acc_size(dt);
+  // operand scratch that the coarse step shares (its own, and the slices'
+  // buffers that the learned candidates borrow) holds FP64 with coarse_f64
+  const size_t e = std::max<size_t>(dt_size(dt), coarse_esz()), ea = std::max<size_t>(acc_size(dt), coarse_esz());
   const int64_t cap64 = std::min<int64_t>((int64_t)(K + 1) * (N + 1), (int64_t)in.n * in.n);
   const int cap = (int)std::max<int64_t>(1, cap64);
   constexpr int NB = 32;  // dot partial blocks
@@ -2309,12 +2329,7 @@ fm_status Flow::features(double h, const double* const* X, const double* const* 
   std::vector<Buf> b(batch);
   double* part = nullptr;
   const int nblk = 16;
-  for (int i = 0; i < batch; ++i)
-    if (!inst[i].B64) {
-      FM_HIP(hipMalloc((void**)&inst[i].B64, (size_t)inst[i].np * inst[i].np * 8));
-      FM_HIP(convert_f64(inst[i].B64, DT_F64, inst[i].A64, inst[i].kind == FM_FLOW_INV_HOMOTOPY ? -1.0 : 0.0,
-                         inst[i].n, inst[i].np, st));
-    }
+  for (int i = 0; i < batch; ++i) FM_TRY(ensure_b64(i, st));
   for (int pass = 0; pass < 2; ++pass) {
     prop.measuring = (pass == 0);
     prop.used = 0;

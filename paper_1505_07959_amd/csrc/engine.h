@@ -119,6 +119,10 @@ struct Flow {
   bool autotune = true;
   int force_bm = 0, force_bk = 0;  // option tile=<bm>x<bk>: fixed product tile (flow dtype)
   int force_pad = 0;                // option pad=64|128|256: fixed padding multiple
+  bool coarse64 = false;            // option coarse_f64=1: coarse-step products in FP64
+  // bytes per element of the coarse step's operand scratch
+  size_t coarse_esz() const { return coarse64 ? 8 : dt_size(dt); }
+  fm_status ensure_b64(int i, hipStream_t st);
   std::string autotune_cache;
   Ring ring;
   Arena work;      // parareal workspace

@@ -146,7 +146,7 @@ def batched(count=512, tol=1e-3):
             "residual_max": max(s["residual"] for s in stats)}
 
 
-def learned_vs_euler(kind=fm.FM_FLOW_INV_HOMOTOPY, dtype=None, tol=None):
+def learned_vs_euler(kind=fm.FM_FLOW_INV_HOMOTOPY, dtype=None, tol=None, options=""):
     """Learned vs Euler coarse step: the n = 2048 homotopy (N = 128, S = 8,
     FP64, to 1e-8) or the n = 8192 X - XAX flow (N = 32, S = 16, T = 30,
     FP16 products, to 1e-3), each after one warm-up solve of the flow."""
@@ -161,7 +161,7 @@ def learned_vs_euler(kind=fm.FM_FLOW_INV_HOMOTOPY, dtype=None, tol=None):
     tol = tol or tl
     Ad = torch.from_numpy(A).cuda()
     model = eval_coarse.DEFAULT_MODEL[kind]
-    flow = fm.fm_flow_create([(kind, Ad)], dt, "coarse_model=%s" % model)
+    flow = fm.fm_flow_create([(kind, Ad)], dt, "coarse_model=%s" % model + (";" + options if options else ""))
     out = torch.empty((n, n), dtype=torch.float64, device="cuda")
     res = []
     try:
@@ -171,8 +171,8 @@ def learned_vs_euler(kind=fm.FM_FLOW_INV_HOMOTOPY, dtype=None, tol=None):
             prm = {"T": T, "N": N, "fine_steps": S, "max_iter": N, "tol": tol, "coarse": coarse}
             (st, stats), sec = _timed(lambda: fm.fm_parareal_solve(flow, None, [out], [prm]))
             s = stats[0]
-            res.append({"workload": "%s_n%d_N%d_S%d_%s_tol%g_%s" % ("homotopy" if kind == 1 else "steady", n, N, S,
-                                                                    dt, tol, name),
+            res.append({"workload": "%s_n%d_N%d_S%d_%s_tol%g_%s%s" % ("homotopy" if kind == 1 else "steady", n, N, S,
+                                                                      dt, tol, name, "_" + options if options else ""),
                         "iterations": s["iters"], "seconds": sec, "serial_fine_seconds": serial,
                         "rel_diff_vs_serial_fine": float(torch.linalg.norm(out - Xs[0]) / torch.linalg.norm(Xs[0])),
                         "restarts": s["learned_restarts"], "status": st})
@@ -185,6 +185,7 @@ ROWS = {"example1": example1, "exp": exp_variants, "aima": aima, "cos": cosine, 
         "batched_tol1e-2": lambda: batched(tol=1e-2),
         "learned": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY),
         "learned_f32": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY, "f32", 1e-6),
+        "learned_f32_coarse64": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY, "f32", 1e-7, "coarse_f64=1"),
         "learned_steady": lambda: learned_vs_euler(fm.FM_FLOW_INV_STEADY)}
 
 

@@ -119,10 +119,11 @@ def test_features_match_oracle(kind):
     assert np.allclose(mu, [np.mean((lam - 1) ** j) for j in (1, 2, 3, 4)], rtol=1e-10)
 
 
-@pytest.mark.parametrize("kind,T,N,S,dtype,bar", [(HOMOTOPY, 1.0, 16, 8, "f64", 1e-10),
-                                                   (STEADY_INV, 12.0, 32, 8, "f64", 1e-10),
-                                                   (HOMOTOPY, 1.0, 16, 8, "f32", 1e-5)])
-def test_learned_parareal_matches_oracle(kind, T, N, S, dtype, bar):
+@pytest.mark.parametrize("kind,T,N,S,dtype,bar,options", [(HOMOTOPY, 1.0, 16, 8, "f64", 1e-10, None),
+                                                           (STEADY_INV, 12.0, 32, 8, "f64", 1e-10, None),
+                                                           (HOMOTOPY, 1.0, 16, 8, "f32", 1e-5, None),
+                                                           (HOMOTOPY, 1.0, 16, 8, "f32", 1e-5, "coarse_f64=1")])
+def test_learned_parareal_matches_oracle(kind, T, N, S, dtype, bar, options):
     """A network whose output is its last bias (exact in FP32): both sides use
     the same coefficients c = c_Euler(h) + b4, including the fallback choice."""
     from paper_1505_07959_amd import fm
@@ -138,7 +139,7 @@ def test_learned_parareal_matches_oracle(kind, T, N, S, dtype, bar):
     salg = SpectralAlgebra(Q, lam)
     ref = learned.parareal_learned(salg, kind, lam, salg.eye(), T, N, 1, S, 6, 0.0,
                                    lambda t, h: learned.euler_coeffs(kind, h) + b4)
-    flow = fm.fm_flow_create([(kind, dev(A))], dtype)
+    flow = fm.fm_flow_create([(kind, dev(A))], dtype, options)
     try:
         fm.fm_flow_set_coarse_model(flow, kind, theta, norm)
         out = empty(n)

@@ -66,6 +66,29 @@ def test_coarse_propagate_matches_oracle(dtype, kind):
     assert e <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16", "bf16x3"])
+@pytest.mark.parametrize("kind", [HOMOTOPY, STEADY_INV, SQRT, EXP, INV_LINEAR])
+def test_coarse_propagate_in_fp64_option(dtype, kind):
+    """Option coarse_f64=1: the coarse step of an FP32 or 16-bit flow runs its
+    products in FP64, so it meets the FP64 bar against the oracle."""
+    from paper_1505_07959_amd import fm
+    n = 136
+    say("coarse_propagate coarse_f64 dtype=%s kind=%d n=%d" % (dtype, kind, n))
+    A, X0 = _case(kind, n, 9)
+    t0, t1, steps = 0.0, 0.25, 3
+    ref = integrators.coarse(MatrixAlgebra(n), kind, A, X0, t1, t0, steps)
+    h = fm.fm_flow_create([(kind, dev(A))], dtype, "coarse_f64=1")
+    try:
+        out = empty(n)
+        fm.fm_coarse_propagate(h, t1, t0, steps, fm.FM_COARSE_EULER, [dev(X0)], [out])
+        got = host(out)
+    finally:
+        fm.fm_destroy(h)
+    e = rel(got, ref)
+    say("  rel err %.3e" % e)
+    assert e <= TOL["f64"]
+
+
 def test_batched_mixed_sizes_and_kinds():
     """One flow with problems of different order and kind: every member of the
     grouped launch matches its own oracle propagation."""
