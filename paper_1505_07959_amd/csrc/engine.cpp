@@ -370,7 +370,8 @@ GemmCfg Flow::pick_cfg(int d, int np) {
   // A batch of products of this order large enough that the largest
   // candidate tile fills the GPU too (>= 1024 tiles): a solve's fine phase
   // launches slices x problems products at once, and a batch that only the
-  // small tiles can fill would always elect them.  Scratch stays <= 512 MB.
+  // small tiles can fill would always elect them.  The batch is capped at
+  // 512 MB of scratch, but holds at least one product.
   const size_t np2 = (size_t)np * np;
   const size_t esz = dt_size(d), asz = acc_size(d);
   int bm_max = 0;
