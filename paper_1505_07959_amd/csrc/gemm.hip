@@ -505,22 +505,24 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
   // j of row r at chunk position j ^ aswz(r) of that row: the lane that fills
   // a position loads the chunk that belongs there, and the fragment reads
   // (32 rows at one chunk) fall on distinct banks.
-  constexpr bool ADMA = DT != DT_F64 && DT != DT_F32 && PF == 1;
+  // (the ring below implies it for the 128-wide tiles as well)
+  constexpr bool RING = DT != DT_F64 && DT != DT_F32 && BK == 32 && (BM == 256 || BM == 128);
+  constexpr bool ADMA = DT != DT_F64 && DT != DT_F32 && (PF == 1 || RING);
   constexpr int CPR = BK / (16 / (int)sizeof(T));  // 16-byte chunks per A row
   constexpr int CPR_SH = CPR == 8 ? 3 : CPR == 4 ? 2 : CPR == 2 ? 1 : 0;
   static_assert(!ADMA || CPR == 4 || CPR == 8, "A swizzle assumes 4 or 8 chunks per row");
   static_assert(!ADMA || TR::V == 16 / (int)sizeof(T), "A fragment reads assume one chunk per k-vector");
   auto aswz = [](int r) { return (r ^ (r >> CPR_SH)) & (CPR - 1); };
-  // The 256 x 32 16-bit tiles go further: B comes by LDS DMA as well, into
-  // a ring of NS stages, so NS - 1 K tiles of loads are in flight while one
-  // is computed.  B keeps its row-major global layout in LDS (16-byte chunk
-  // j of k-row r at position j ^ bsw(r)); each lane's eight k-values of one
-  // column are gathered by two transposing LDS reads (ds_read_b64_tr_b16:
-  // within 16 lanes, lane i receives element i % 4 of the 8-byte reads of
-  // lanes 4j + i / 4, j = 0..3).  bsw(r) = 5 (r mod 4) puts the 16 lanes of
-  // such a read (4 rows x 32 bytes) on distinct banks (checked by
-  // enumeration in a 32-bank and in a 64-bank model).
-  constexpr bool RING = ADMA && BM == 256 && BK == 32;
+  // The 256 x 32 and 128 x 32 16-bit tiles go further: B comes by LDS DMA
+  // as well, into a ring of NS stages, so NS - 1 K tiles of loads are in
+  // flight while one is computed.  B keeps its row-major global layout in
+  // LDS (16-byte chunk j of k-row r at position j ^ bsw(r)); each lane's
+  // eight k-values of one column are gathered by two transposing LDS reads
+  // (ds_read_b64_tr_b16: within 16 lanes, lane i receives element i % 4 of
+  // the 8-byte reads of lanes 4j + i / 4, j = 0..3).  bsw(r) = 5 (r mod 4)
+  // puts the 16 lanes of such a read (4 rows x 32 bytes) on distinct banks
+  // for rows of 32 and of 16 chunks (checked by enumeration in a 32-bank and
+  // in a 64-bank model).
   constexpr int NS = RING ? 4 : 2;  // LDS stages
   auto bsw = [](int r) { return 5 * (r & 3); };
   constexpr int PADA = ADMA ? 0 : 16 / (int)sizeof(T);
@@ -533,7 +535,7 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
   constexpr int A_PER_T = A_CHUNKS / NT;
   constexpr int BR_PER_T = BK * BN / W / NT;  // B chunks per thread (ring)
   static_assert(!RING || (BK * BN / W) % NT == 0, "B tile split (ring)");
-  static_assert(!RING || (BN / W) == 32, "the B swizzle assumes 32 chunks per k-row");
+  static_assert(!RING || (BN / W) == 32 || (BN / W) == 16, "the B swizzle assumes 16 or 32 chunks per k-row");
   constexpr int B_PER_T = B_BLOCKS >= NT ? B_BLOCKS / NT : 1;
   // When the tile has fewer B blocks (V rows x 16 bytes) than threads, the
   // RSPLIT threads of a block share its rows (VR each) so that every thread
