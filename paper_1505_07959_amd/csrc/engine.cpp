@@ -370,17 +370,20 @@ GemmCfg Flow::pick_cfg(int d, int np) {
   // A batch of products of this order large enough that the largest
   // candidate tile fills the GPU too (>= 1024 tiles): a solve's fine phase
   // launches slices x problems products at once, and a batch that only the
-  // small tiles can fill would always elect them.  The batch is capped at
-  // 512 MB of scratch, but holds at least one product.
+  // small tiles can fill would always elect them.  That growth stops at
+  // 512 MB of scratch; the base batch (up to 16 products, 128 MB of
+  // operands) is kept even where it is larger, since a trial of one short
+  // launch is too noisy to rank tiles.
   const size_t np2 = (size_t)np * np;
   const size_t esz = dt_size(d), asz = acc_size(d);
   int bm_max = 0;
   for (const GemmCfg& c : cand) bm_max = std::max(bm_max, c.bm);
   const size_t big_tiles = (size_t)(np / bm_max) * (np / bm_max);
   const size_t per_item = np2 * (2 * esz + asz + 8);
-  size_t want = std::max<size_t>(std::min<size_t>(16, ((size_t)1 << 27) / (np2 * 2)), (1024 + big_tiles - 1) / big_tiles);
-  want = std::min<size_t>(want, std::max<size_t>(1, ((size_t)512 << 20) / per_item));
-  const int nb = (int)std::max<size_t>(1, want);
+  const size_t base = std::max<size_t>(1, std::min<size_t>(16, ((size_t)1 << 27) / (np2 * 2)));
+  const size_t fill = (1024 + big_tiles - 1) / big_tiles;
+  const size_t cap = std::max<size_t>(base, ((size_t)512 << 20) / per_item);
+  const int nb = (int)std::min<size_t>(std::max(base, fill), cap);
   void *A = nullptr, *B = nullptr, *C = nullptr, *Kacc = nullptr;
   double* Xs = nullptr;
   GItem* di = nullptr;
