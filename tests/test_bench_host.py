@@ -1,0 +1,48 @@
+"""Host logic of bench.py (no GPU): the oracle baseline's fields, the rule
+that HBM traffic is reported only for the GEMM source it was measured on,
+and the refusal of a multi-GPU run."""
+
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_cpu_baseline_reports_all_and_one_core():
+    n = 64
+    A = np.eye(n) * 1.5
+    r = bench.cpu_baseline(A, n, fine_steps_total=100, coarse_steps_total=10, sample_steps=1)
+    assert r["kind"] == "oracle" and r["unit"] == "solves/s"
+    assert r["value"] > 0 and r["cores"] >= 1
+    assert r["value_one_core"] is None or r["value_one_core"] > 0
+    assert "one core" in r["sample"]
+
+
+def test_traffic_reported_only_for_the_measured_source(tmp_path, monkeypatch):
+    src = json.load(open(bench.TRAFFIC_FILE))
+    key = next(iter(src))
+    per_item = src[key]["bytes_per_item"]
+    good = tmp_path / "good.json"
+    good.write_text(json.dumps(src))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(good))
+    assert bench.traffic_for(key, 3) == per_item * 3
+    stale = dict(src)
+    stale[key] = dict(src[key], gemm_sha256="0" * 64)
+    bad = tmp_path / "stale.json"
+    bad.write_text(json.dumps(stale))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(bad))
+    assert bench.traffic_for(key, 3) is None
+    assert bench.traffic_for("no_such_kernel", 3) is None
+
+
+def test_multi_gpu_run_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
