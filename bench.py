@@ -111,8 +111,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (time slices would shard over "
-              "GPUs as described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (time slices would shard over "
+              "GPUs, one range of slices per GPU); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -40,7 +40,7 @@ typedef enum {
   FM_ERR_NOMEM = -2,          /* device allocation failed */
   FM_ERR_DEVICE = -3,         /* HIP runtime error */
   FM_ERR_NONFINITE = -4,      /* an iterate became Inf/NaN (e.g. A(t) singular) */
-  FM_ERR_UNSUPPORTED = -5     /* valid request this build does not implement */
+  FM_ERR_UNSUPPORTED = -5     /* valid request the library does not implement */
 } fm_status;
 
 /* The matrix flows dX/dt = F(X). */
