@@ -186,7 +186,8 @@ ROWS = {"example1": example1, "exp": exp_variants, "aima": aima, "cos": cosine, 
         "learned": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY),
         "learned_f32": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY, "f32", 1e-6),
         "learned_f32_coarse64": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY, "f32", 1e-7, "coarse_f64=1"),
-        "learned_steady": lambda: learned_vs_euler(fm.FM_FLOW_INV_STEADY)}
+        "learned_steady": lambda: learned_vs_euler(fm.FM_FLOW_INV_STEADY),
+        "learned_steady_coarse64": lambda: learned_vs_euler(fm.FM_FLOW_INV_STEADY, options="coarse_f64=1")}
 
 
 def main():
