@@ -1,15 +1,28 @@
 """Benchmark: parareal solves/s and fine-propagator MFMA TFLOP/s on one MI355X.
 
-Workload (one step = one whole parareal solve): inverse homotopy flow
-dX/dt = X (I - A) X, X(0) = I, T = 1, on the n = 4096 SPD matrix with
-lam ~ U[0.05, 4] (seed 2); N = 64 slices, one forward-Euler coarse step and
-16 RK4 fine steps per slice; all slice fine solves of an iteration batched in
-one grouped GEMM launch per product; FP64 correction; the solve stops when
-the increment max_n ||U^{k+1}_n - U^k_n||_F / ||U^{k+1}_n||_F <= 1e-8.
-Products run in FP64 on MFMA by default: with FP32 products the increment of
-this problem stalls near 1.6e-7 (rounding noise of the FP32 fine propagator)
-and reaches 1e-8 only at exact termination k = N, so the FP32 run is measured
-with --dtype f32 (and its own --tol).
+Workload: inverse homotopy flow dX/dt = X (I - A) X, X(0) = I, T = 1, on the
+n = 4096 SPD matrix with lam ~ U[0.05, 4] (seed 2); N = 64 slices, one
+forward-Euler coarse step and 16 RK4 fine steps per slice; all slice fine
+solves of an iteration batched in one grouped GEMM launch per product, the
+launches of one RK4 step replayed from a hipGraph; FP64 correction; the
+solve stops when max_n ||U^{k+1}_n - U^k_n||_F / ||U^{k+1}_n||_F <= 1e-8.
+Products run in FP64 on MFMA by default: with FP32 products parareal
+converges to the FP32 fine solution, 1.8e-6 away from the FP64 one, so only
+the FP64 run reaches 1e-8 relative error (--dtype selects another).
+
+One step = one parareal iteration (the batched fine phase over the live
+slices, the FP64 correction sweep, the stop test).  The timed region holds
+whole converged solves run back to back, about 9 iterations each: solves
+are added until `--steps` iterations are covered, unless the next solve
+would end past the wall-clock budget (--budget-s, counted from the start of
+the process, leaving room for the CPU baseline); `steps` reports the
+iterations actually timed.  Warm-up: min(--warmup, 2) iterations of a
+truncated solve (workspace allocation, autotuning, graph instantiation).
+
+value = converged solves / timed wall time.  roofline: the fine-step GEMM
+launches (affine and RK4-epilogue products of every RK4 step), timed with
+HIP events on the solve's stream around each hipGraph replay of one RK4
+step; achieved = algorithmic flops (2 n^3 per slice product) / time.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -21,16 +34,18 @@ import os
 import sys
 import time
 
+T_PROCESS = time.time()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # TFLOP/s, dense MFMA; split BF16 does three BF16 products per algorithmic one
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.0, "f16": 2516.0, "bf16x3": 2516.0 / 3}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+METRIC = "parareal solves/s + MFMA TFLOP/s at 1e-8 rel err; learned vs Euler coarse"
 
 
 def log(msg):
-    print("[bench] " + msg, file=sys.stderr, flush=True)
+    print("[bench %6.1fs] %s" % (time.time() - T_PROCESS, msg), file=sys.stderr, flush=True)
 
 
 def traffic_for(kernel_key, items_per_launch):
@@ -90,12 +105,33 @@ def cpu_baseline(A, n, fine_steps_total, coarse_steps_total, sample_steps):
                       "thread, scaled by 8" % (sample_steps, n, t_step, fine_steps_total, coarse_steps_total)}
 
 
+def plan_next_solve(now, solve_s, steps_done, steps_target, budget_s, reserve_s):
+    """Whether another whole solve goes into the timed region: more steps are
+    wanted and, at the last solve's duration, it ends within the budget
+    (seconds since process start) with `reserve_s` left over."""
+    if steps_done >= steps_target:
+        return False
+    return now + solve_s + reserve_s <= budget_s
+
+
+def solve_work(n, N, S, iters):
+    """Fine RK4 steps and coarse Euler steps of a solve of `iters` iterations:
+    iteration k re-solves the slices n >= k; the sweep of iteration k takes a
+    coarse step on every slice after the k-th, Step 0 on all N."""
+    fine = sum(N - k for k in range(iters)) * S
+    coarse = N + sum(N - k - 1 for k in range(iters))
+    return fine, coarse
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=9, help="parareal iterations to time (whole solves)")
+    ap.add_argument("--warmup", type=int, default=1, help="warm-up iterations (at most 2 are run)")
+    ap.add_argument("--budget-s", type=float, default=450.0,
+                    help="wall-clock budget from process start: no timed solve is started that would end later")
     ap.add_argument("--dtype", default="f64", choices=["f32", "f64", "bf16", "f16", "bf16x3"])
+    ap.add_argument("--coarse", default="euler", choices=["euler", "learned"])
     ap.add_argument("--tile", default=None, help="fixed product tile <bm>x<bk> instead of the autotuned one")
     ap.add_argument("--coarse-f64", action="store_true", help="coarse-step products in FP64 (FP32/16-bit runs)")
     ap.add_argument("--n", type=int, default=4096)
@@ -103,7 +139,7 @@ def main():
     ap.add_argument("--fine-steps", type=int, default=16)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=64)
-    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--cpu-sample-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serial", action="store_true",
                     help="also time the serial fine solve after the benchmark (off by default: its one-product "
@@ -115,38 +151,58 @@ def main():
               "GPUs, one range of slices per GPU); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1505_07959_amd import fm, inputs
 
     n, N, S = args.n, args.slices, args.fine_steps
     log("building input n=%d" % n)
-    A, Q, lam = inputs.large_problem(n)
+    A, Q, lam = inputs.large_problem(n) if n == 4096 else inputs.spd(n, "uniform", 0.05, 4.0, 2)
     Ad = torch.from_numpy(A).cuda()
     out = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    coarse = fm.FM_COARSE_LEARNED if args.coarse == "learned" else fm.FM_COARSE_EULER
     prm = {"T": 1.0, "N": N, "coarse_steps": 1, "fine_steps": S, "max_iter": args.max_iter, "tol": args.tol,
-           "coarse": fm.FM_COARSE_EULER, "max_refine": 0}
-    opts = "timing=1;verbose=1" + (";tile=" + args.tile if args.tile else "") + (";coarse_f64=1" if args.coarse_f64 else "")
+           "coarse": coarse, "max_refine": 0}
+    opts = "timing=1;verbose=1" + (";tile=" + args.tile if args.tile else "") + \
+           (";coarse_f64=1" if args.coarse_f64 else "")
+    if coarse == fm.FM_COARSE_LEARNED:
+        opts += ";coarse_model=" + os.path.join(ROOT, "paper_1505_07959_amd", "models", "homotopy_n256.fmw")
+    log("creating the flow (autotuning the product tiles)")
     h = fm.fm_flow_create([(fm.FM_FLOW_INV_HOMOTOPY, Ad)], args.dtype, opts)
     stream = torch.cuda.current_stream()
 
-    def one():
-        st, stats = fm.fm_parareal_solve(h, None, [out], [prm], stream=stream)
+    def one(max_iter):
+        st, stats = fm.fm_parareal_solve(h, None, [out], [dict(prm, max_iter=max_iter)], stream=stream)
         return st, stats[0]
 
-    for w in range(args.warmup):
+    warm = min(args.warmup, 2)
+    if warm > 0:
         t = time.perf_counter()
-        st, s = one()
-        log("warmup %d: %.2f s, iters %d, status %d" % (w, time.perf_counter() - t, s["iters"], st))
+        st, s = one(warm)
+        log("warm-up: %d iterations in %.2f s (status %d)" % (s["iters"], time.perf_counter() - t, st))
+
+    # timed region: whole solves, back to back
+    reserve = 0.0 if args.no_cpu_baseline else 30.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = []
-    for k in range(args.steps):
-        st, s = one()
-        stats.append(s)
-        log("step %d: iters %d, increment %.3e, status %d" % (k, s["iters"], s["increment"], st))
+    solves = []
+    last = None
+    while True:
+        ts = time.perf_counter()
+        st, s = one(args.max_iter)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ts
+        solves.append((st, s, dt))
+        last = dt
+        done = sum(x[1]["iters"] for x in solves)
+        log("solve %d: %d iterations, increment %.3e, status %d, %.2f s (%d steps timed)" %
+            (len(solves), s["iters"], s["increment"], st, dt, done))
+        if not plan_next_solve(time.time() - T_PROCESS, last, done, args.steps, args.budget_s, reserve):
+            break
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    steps = sum(x[1]["iters"] for x in solves)
+    if steps < args.steps:
+        log("wall-clock budget: %d of %d requested steps timed (%d whole solves)" % (steps, args.steps, len(solves)))
 
     # outside the timed region: the serial fine solve that the parareal
     # iteration converges to (N*S RK4 steps from X0 = I on one GPU), for the
@@ -162,59 +218,66 @@ def main():
         t = time.perf_counter()
         fm.fm_fine_propagate(h, 1.0, 0.0, N * S, [X0], [Xs], stream=stream)
         torch.cuda.synchronize()
-        ts = time.perf_counter() - t
-        serial = {"seconds": ts, "rk4_steps": N * S, "tflops": N * S * 16.0 * n ** 3 / ts / 1e12,
+        tser = time.perf_counter() - t
+        serial = {"seconds": tser, "rk4_steps": N * S, "tflops": N * S * 16.0 * n ** 3 / tser / 1e12,
                   "rel_diff_vs_parareal": float(torch.linalg.norm(out - Xs) / torch.linalg.norm(Xs))}
-        log("serial fine: %.2f s (parareal solve %.2f s), rel diff %.2e" % (ts, elapsed / args.steps,
-                                                                           serial["rel_diff_vs_parareal"]))
+        log("serial fine: %.2f s, rel diff %.2e" % (tser, serial["rel_diff_vs_parareal"]))
     fm.fm_destroy(h)
 
-    s = stats[-1]
-    converged = all(x["status"] == 0 for x in stats)
-    solves_per_s = args.steps / elapsed if converged else 0.0
-    avg_launch_ms = s["fine_ms"] / max(1, s["fine_launches"])
-    flops_per_launch = s["fine_flops"] / max(1, s["fine_launches"])
-    achieved = flops_per_launch / (avg_launch_ms * 1e-3) / 1e12
-    iters = s["iters"]
-    fine_steps_total = sum(N - k for k in range(iters)) * S
-    coarse_steps_total = N + sum(N - k - 1 for k in range(iters))
-    total_fine_flops = fine_steps_total * 16.0 * n ** 3
-    log("iters %d  hist %s" % (iters, ["%.1e" % x for x in s["hist"]]))
-    log("fine RK4-epilogue GEMM: %d launches, avg %.3f ms, %.1f TFLOP/s; fine phases %.2f s of %.2f s/solve" %
-        (s["fine_launches"], avg_launch_ms, achieved, s["fine_phase_ms"] / 1e3, elapsed / args.steps))
+    converged = [x for x in solves if x[0] == fm.FM_OK]
+    solves_per_s = len(converged) / elapsed
+    launches = sum(x[1]["fine_launches"] for x in solves)
+    fine_ms = sum(x[1]["fine_ms"] for x in solves)
+    fine_flops = sum(x[1]["fine_flops"] for x in solves)
+    avg_launch_ms = fine_ms / max(1, launches)
+    flops_per_launch = fine_flops / max(1, launches)
+    achieved = fine_flops / (fine_ms * 1e-3) / 1e12 if fine_ms > 0 else 0.0
+    iters = [x[1]["iters"] for x in solves]
+    s = solves[-1][1]
+    fine_steps_total, coarse_steps_total = solve_work(n, N, S, s["iters"])
+    total_fine_flops = sum(solve_work(n, N, S, k)[0] for k in iters) * 16.0 * n ** 3
+    log("iterations per solve %s, hist %s" % (iters, ["%.1e" % x for x in s["hist"]]))
+    log("fine-step GEMM: %d launches, avg %.3f ms, %.1f TFLOP/s; fine phases %.1f s of %.1f s timed" %
+        (launches, avg_launch_ms, achieved, sum(x[1]["fine_phase_ms"] for x in solves) / 1e3, elapsed))
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (%d oracle RK4 steps at n=%d)" % (args.cpu_sample_steps, n))
         cpu = cpu_baseline(A, n, fine_steps_total, coarse_steps_total, args.cpu_sample_steps)
 
-    key = "gemm_%s_rk4_n%d" % (args.dtype, n)
+    key = "gemm_%s_fine_step_n%d" % (args.dtype, n)
     res = {
-        "metric": "parareal solves/s + MFMA TFLOP/s at 1e-8 rel err; learned vs Euler coarse",
+        "metric": METRIC,
         "value": solves_per_s,
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": elapsed / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": "inverse homotopy dX/dt=X(I-A)X, n=%d SPD lam~U[0.05,4] seed 2, N=%d slices, "
-                               "RK4 %d steps/slice, Euler 1 step/slice, %s MFMA products, %s, FP64 correction, "
-                               "stop at increment <= %g" % (n, N, S, args.dtype,
+                               "RK4 %d steps/slice, %s coarse 1 step/slice, %s MFMA products, %s, FP64 correction, "
+                               "stop at increment <= %g" % (n, N, S, args.coarse, args.dtype,
                                                             "FP32 fine-solve state" if args.dtype in ("bf16", "f16", "bf16x3")
                                                             else "FP64 state", args.tol),
-                   "n": n, "slices": N, "fine_steps": S, "coarse_steps": 1, "tol": args.tol,
-                   "iterations": iters, "converged": converged,
-                   "fine_tflops_whole_solve": total_fine_flops / (elapsed / args.steps) / 1e12},
+                   "step": "one parareal iteration (batched fine phase, FP64 correction sweep, stop test); "
+                           "whole converged solves timed back to back",
+                   "n": n, "slices": N, "fine_steps": S, "coarse_steps": 1, "coarse": args.coarse, "tol": args.tol,
+                   "solves_timed": len(solves), "solves_converged": len(converged),
+                   "iterations_per_solve": iters, "seconds_per_solve": [round(x[2], 3) for x in solves],
+                   "steps_requested": args.steps, "warmup_requested": args.warmup,
+                   "learned_restarts": [x[1]["learned_restarts"] for x in solves],
+                   "fine_tflops_whole_solve": total_fine_flops / elapsed / 1e12},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[args.dtype], "unit": "TFLOP/s",
                      "frac": achieved / PEAK[args.dtype],
                      "traffic": traffic_for(key, flops_per_launch / (2.0 * n ** 3)),
-                     "kernel": "gemm_kernel RK4-epilogue (fine propagator), avg of %d launches, %.3e flop/launch"
-                               % (s["fine_launches"], flops_per_launch)},
+                     "kernel": "gemm_kernel fine-step launches (affine + RK4-epilogue products), HIP events around "
+                               "each graph replay of one RK4 step: %d launches, avg %.3f ms, %.3e flop/launch"
+                               % (launches, avg_launch_ms, flops_per_launch)},
         "cpu_baseline": cpu,
         "serial_fine": serial,
     }

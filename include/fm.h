@@ -137,7 +137,8 @@ typedef struct {
 } fm_params;
 
 typedef struct {
-  int32_t iters;           /* parareal iterations performed */
+  int32_t iters;           /* parareal iterations performed, those before a
+                              learned-step restart included (<= max_iter) */
   int32_t refine_steps;    /* refinement updates performed */
   int32_t learned_slices;  /* slice solves that used the learned step in the
                               last iteration (0 for Euler)                  */
@@ -146,15 +147,19 @@ typedef struct {
   double residual_before;  /* FP64 relative residual before refinement:
                               ||I - A X||_F / sqrt(n) or ||A - X^2||_F / ||A||_F */
   double residual;         /* the same after refinement */
-  double hist[64];         /* increment of iterations 1..64 */
+  double hist[64];         /* increment of iterations 1..64, in the order
+                              run (across a restart)                        */
   /* Filled when the flow was created with option "timing=1" (else 0): HIP
-   * event timing, on the solve's stream, of every launch of the fine
-   * propagator's second product of an RK4 stage (the RK4-epilogue GEMM).   */
-  int32_t fine_launches;   /* number of such launches */
+   * event timing, on the solve's stream, of the fine propagator's GEMM
+   * launches (both products of every RK4 stage).  With graphs on (the
+   * default) the events bracket each replay of one RK4 step's launches;
+   * with graph=0 they bracket every launch.                                */
+  int32_t fine_launches;   /* number of GEMM launches timed */
   int32_t learned_restarts; /* times a learned-coarse problem restarted from
                                Step 0 with Euler after a non-finite iterate */
   double fine_ms;          /* their summed duration, milliseconds */
-  double fine_flops;       /* their algorithmic flops: 2 n^3 per problem-slice */
+  double fine_flops;       /* their algorithmic flops: 2 n^3 per problem-slice
+                              product */
   double fine_phase_ms;    /* duration of the whole batched fine phases */
   int32_t basis_size;      /* FM_PARAREAL_MODIFIED: blocks in the basis at
                               the end (0 for the classical variant) */
@@ -183,7 +188,7 @@ typedef struct {
  * 256x32, 64x64; problems are then padded to a multiple of 64, and the tile
  * is ignored for a problem whose padded order it does not divide),
  * graph=0|1 (default 1: the launches of one RK4 step of a fine phase are
- * captured in a hipGraph and replayed for every step; off while timing=1).
+ * captured in a hipGraph and replayed for every step).
  * Tile shapes and graphs never change results; the padded order can change
  * them at rounding level only (the summation order of norms and dot products).
  * out: host; receives the handle.  Returns FM_ERR_INVALID for batch < 1,
@@ -221,7 +226,6 @@ fm_status fm_coarse_propagate(fm_flow f, double t_next, double t_cur, int32_t st
                               int32_t coarse, const double* const* X_in,
                               double* const* X_out, void* hip_stream);
 
-/* Release the flow and all its device memory.  NULL is accepted. */
 /* Sec. 4, Example 5, Alg. 8 (acceleration of convergence in time towards
  * A^{-1}): for every problem of the flow, all of kind FM_FLOW_INV_LINEAR,
  *     X_{k+1} = X_k + dt (I - A X_k + u_k),   u_{k+1} = (I - dt A) u_k,
@@ -259,6 +263,7 @@ fm_status fm_aima(fm_flow f, const double* const* X0, const double* const* E, do
 fm_status fm_cos(const double* A, int64_t n, int64_t lda, int32_t dtype, const fm_params* prm, double* C_out,
                  int32_t* m_out, fm_stats* stats, const char* options, void* hip_stream);
 
+/* Release the flow and all its device memory.  NULL is accepted. */
 void fm_destroy(fm_flow f);
 
 /* Thread-local message of the last error (empty string if none). */

@@ -117,12 +117,12 @@ hipEvent_t Flow::next_event() {
 }
 
 fm_status Flow::collect_timing() {
-  for (auto& pr : ev_pairs) {
+  for (const Timed& pr : ev_pairs) {
     float ms = 0.f;
-    FM_HIP(hipEventElapsedTime(&ms, ev[pr.first], ev[pr.first + 1]));
+    FM_HIP(hipEventElapsedTime(&ms, ev[pr.ev], ev[pr.ev + 1]));
     t_ms += ms;
-    t_flops += pr.second;
-    t_launches++;
+    t_flops += pr.flops;
+    t_launches += pr.launches;
   }
   for (int i : phase_pairs) {
     float ms = 0.f;
@@ -763,7 +763,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
       }
     return FM_OK;
   };
-  if (use_graph && cap_stream && !timing && units > 1) {
+  if (use_graph && cap_stream && units > 1) {
     // capture the launches of one unit once, replay the graph for every unit
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
@@ -783,13 +783,35 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
     pending_graph.push_back(g);
     pending_exec.push_back(ge);
     pending_stream.push_back(st);
-    for (int u = 0; u < units; ++u) FM_HIP(hipGraphLaunch(ge, st));
+    // with timing=1 each replay (one step: every GEMM launch of the unit) is
+    // bracketed by events on the solve's stream
+    double unit_flops = 0;
+    for (const Launch& L : seq) unit_flops += L.flops;
+    for (int u = 0; u < units; ++u) {
+      int idx = -1;
+      if (timing) {
+        idx = (int)ev_used;
+        hipEvent_t a = next_event(), b = next_event();
+        if (a && b) FM_HIP(hipEventRecord(a, st));
+        else idx = -1;
+      }
+      FM_HIP(hipGraphLaunch(ge, st));
+      if (idx >= 0) {
+        FM_HIP(hipEventRecord(ev[idx + 1], st));
+        ev_pairs.push_back(Timed{idx, unit_flops, (int)seq.size()});
+      }
+    }
     FM_TRY(launch_tail());
-    return widen_back();
+    FM_TRY(widen_back());
+    if (timing && phase_ev >= 0) {
+      FM_HIP(hipEventRecord(ev[phase_ev + 1], st));
+      phase_pairs.push_back(phase_ev);
+    }
+    return FM_OK;
   }
   for (int u = 0; u < units; ++u)
     for (const Launch& L : seq) {
-      const bool rec = timing && L.epi == fepi;
+      const bool rec = timing;
       int idx = -1;
       if (rec) {
         idx = (int)ev_used;
@@ -800,7 +822,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
       FM_HIP(launch_gemm(L.cfg, L.epi, L.items, L.ts, L.n, L.total, L.grid, nullptr, st));
       if (idx >= 0) {
         FM_HIP(hipEventRecord(ev[idx + 1], st));
-        ev_pairs.push_back({idx, L.flops});
+        ev_pairs.push_back(Timed{idx, L.flops, 1});
       }
     }
   FM_TRY(launch_tail());
@@ -1262,8 +1284,11 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
     FM_TRY(step0(ids));
   }
 
-  // ---- iterations (each problem counts its own: kk[i] iterations done)
-  std::vector<int> live(batch, 0), kk(batch, 0), restarts(batch, 0);
+  // ---- iterations (each problem counts its own: kk[i] iterations since its
+  // last Step 0, which is also the number of leading slices that equal the
+  // serial fine solution; total[i] iterations including those before a
+  // restart, the count that max_iter bounds and the stats report)
+  std::vector<int> live(batch, 0), kk(batch, 0), total(batch, 0), restarts(batch, 0);
   std::vector<fm_status> ist(batch, FM_OK);
   std::vector<double> lastinc(batch, 0.0);
   std::vector<std::vector<double>> hist(batch);
@@ -1274,8 +1299,13 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
     int64_t np2 = (int64_t)inst[i].np * inst[i].np;
     nblk = std::max<int>(nblk, (int)std::min<int64_t>(256, (np2 + 4095) / 4096));
   }
-  FM_TRY(ensure_part(npairs * nblk * 3 + npairs * 3 + npairs * 2));
-  double* d_red = part + npairs * nblk * 3;
+  // partials: the correction's (3 per block and pair) or the learned
+  // candidates' defect dots (two per pair, 16 blocks each), then the reduced
+  // triples and the candidate defects
+  const int cand_blk = 16;
+  const size_t part_n = npairs * (size_t)std::max(3 * nblk, 2 * cand_blk);
+  FM_TRY(ensure_part(part_n + npairs * 3 + npairs * 2));
+  double* d_red = part + part_n;
   double* d_cand = d_red + npairs * 3;  // defects of the learned / Euler candidates
 
   for (int round = 0;; ++round) {
@@ -1345,8 +1375,12 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
         FM_TRY(run_coarse_mixed(ce));
         FM_TRY(run_coarse_mixed(cl));
         void* d = nullptr;
+        if (di.size() * cand_blk > part_n || di.size() > 2 * npairs) {
+          set_error("internal: %zu candidate dots exceed the partials buffer", di.size());
+          return FM_ERR_INVALID;
+        }
         FM_TRY(push(di.data(), di.size() * sizeof(DotItem), &d, st));
-        FM_HIP(launch_dots((const DotItem*)d, (int)di.size(), part, 16, d_cand, st));
+        FM_HIP(launch_dots((const DotItem*)d, (int)di.size(), part, cand_blk, d_cand, st));
         FM_HIP(hipMemcpyAsync(hredu, d_cand, npairs * 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         FM_HIP(hipStreamSynchronize(st));
         ring.reset();
@@ -1411,11 +1445,13 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
         if (r[2] != 0.0) bad = true;
       }
       kk[i]++;
+      total[i]++;
       lastinc[i] = inc;
       hist[i].push_back(inc);
       if (bad) {
-        if (cmode[i] == FM_COARSE_LEARNED) {
-          // the learned step diverged in a sweep: restart with Euler
+        if (cmode[i] == FM_COARSE_LEARNED && total[i] < prm[i].max_iter) {
+          // the learned step diverged in a sweep: restart from Step 0 with
+          // Euler; the iterations so far still count against max_iter
           cmode[i] = FM_COARSE_EULER;
           learned_count[i] = 0;
           restarts[i]++;
@@ -1429,7 +1465,7 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
       }
       if (inc <= prm[i].tol || kk[i] >= prm[i].N) {
         live[i] = 0;
-      } else if (kk[i] >= prm[i].max_iter) {
+      } else if (total[i] >= prm[i].max_iter) {
         live[i] = 0;
         ist[i] = FM_WARN_NOT_CONVERGED;
       }
@@ -1439,7 +1475,7 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
       double worst = 0.0;
       int nlive = 0;
       for (int i = 0; i < batch; ++i) {
-        if (live[i] || kk[i] > 0) worst = std::max(worst, lastinc[i]);
+        if (live[i] || total[i] > 0) worst = std::max(worst, lastinc[i]);
         nlive += live[i];
       }
       const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
@@ -1448,7 +1484,7 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
       fflush(stderr);
     }
   }
-  std::vector<int> iters = kk;
+  std::vector<int> iters = total;
 
   // ---- result, residual and refinement
   std::vector<double*> X(batch);

@@ -137,7 +137,7 @@ struct Flow {
   // optional HIP-event timing of the fine propagator (option timing=1)
   bool timing = false;
   bool verbose = false;  // option verbose=1: one stderr line per parareal iteration
-  bool use_graph = true; // option graph=0|1: replay the RK4 step of a fine phase from a hipGraph
+  bool use_graph = true; // option graph=0|1: replay the RK4 step of a fine phase from a hipGraph (timing=1 too)
   hipStream_t cap_stream = nullptr;          // capture stream (default priority)
   std::vector<hipGraphExec_t> pending_exec;  // executable graphs kept until the next synchronisation
   std::vector<hipGraph_t> pending_graph;
@@ -145,7 +145,14 @@ struct Flow {
   void release_graphs();
   std::vector<hipEvent_t> ev;      // event pool
   size_t ev_used = 0;
-  std::vector<std::pair<int, double>> ev_pairs;  // (index of start event, flops) of RK4-epilogue launches
+  // one timed interval: start-event index, algorithmic flops, GEMM launches
+  // (one RK4 step of a fine phase, replayed from its graph, or one launch)
+  struct Timed {
+    int ev;
+    double flops;
+    int launches;
+  };
+  std::vector<Timed> ev_pairs;
   std::vector<int> phase_pairs;    // start-event index of each fine phase
   int64_t t_launches = 0;
   double t_ms = 0, t_flops = 0, t_phase_ms = 0;

@@ -46,3 +46,23 @@ def test_multi_gpu_run_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_timed_region_takes_whole_solves_within_the_budget():
+    # more steps wanted and the next solve (as long as the last) fits: go on
+    assert bench.plan_next_solve(now=200.0, solve_s=150.0, steps_done=9, steps_target=20, budget_s=450.0,
+                                 reserve_s=30.0)
+    # it would end past the budget once the CPU baseline's reserve is counted
+    assert not bench.plan_next_solve(now=300.0, solve_s=150.0, steps_done=18, steps_target=20, budget_s=450.0,
+                                     reserve_s=30.0)
+    # enough steps timed
+    assert not bench.plan_next_solve(now=10.0, solve_s=1.0, steps_done=20, steps_target=20, budget_s=450.0,
+                                     reserve_s=0.0)
+
+
+def test_solve_work_counts_live_slices():
+    # iteration k re-solves slices k..N-1; the sweep of iteration k takes a
+    # coarse step on slices k+1..N-1, Step 0 on all N
+    fine, coarse = bench.solve_work(4096, 4, 2, 3)
+    assert fine == (4 + 3 + 2) * 2
+    assert coarse == 4 + (3 + 2 + 1)
