@@ -33,11 +33,21 @@ come from a small network.  Reading used (the paper does not define this part):
   chosen propagator G_n serves both terms of the correction
   G_n(U^{k+1}_n) - G_n(U^k_n).  Step 0 uses the learned step unless it is not
   finite.
+* Restart: if a sweep still produces a non-finite iterate while the learned
+  step is in use, the problem starts over from Step 0 with the Euler step on
+  every slice (plain Alg. 1 from then on).  The iteration that failed counts:
+  max_iter bounds all iterations, those before the restart included, and
+  the increment history keeps them in order; the exactness bound k = N
+  counts from the restart.  A non-finite sweep with Euler in use, or one
+  that reaches max_iter, ends the run as non-finite.
 
 Parity: pinned by the Euler member reproducing forward Euler, by the Taylor
 member's fourth-order local error against the closed-form homotopy, by the
-Gram-form defect matching the directly computed defect, and by the LS solution
-matching a least-squares solve on the flattened basis
+Gram-form defect matching the directly computed defect, by the LS solution
+matching a least-squares solve on the flattened basis, by the per-slice
+choice on scalar problems whose defects have closed forms (learned better on
+some slices and worse on others; a choice that flips between iterations),
+and by the restart reducing to plain Euler parareal
 (tests/test_oracle_learned.py).
 """
 
@@ -146,11 +156,21 @@ def _finite(alg, X):
 
 
 def parareal_learned(alg, kind, A, u0, T, N, coarse_steps, fine_steps,
-                     max_iter, tol, coeff_fn):
-    """Alg. 1 with the learned coarse step and the per-slice Euler fallback."""
+                     max_iter, tol, coeff_fn, fine=None):
+    """Alg. 1 with the learned coarse step, the per-slice Euler fallback and
+    the restart with Euler after a non-finite sweep.
+
+    fine(n, x), if given, replaces the RK4 fine propagator of slice n (tests
+    use it to force a non-finite sweep).  Returns the final iterates U, the
+    iteration count (all iterations, across a restart), the increments, every
+    iterate list, the per-slice choices of every iteration (those of the
+    coarse sweep first), the number of restarts and a status ("ok",
+    "max_iter" or "nonfinite")."""
     t = [n * T / N for n in range(N + 1)]
 
     def F(n, x):
+        if fine is not None:
+            return fine(n, x)
         return integrators.fine(alg, kind, A, x, t[n + 1], t[n], fine_steps)
 
     def GL(n, x):
@@ -159,27 +179,38 @@ def parareal_learned(alg, kind, A, u0, T, N, coarse_steps, fine_steps,
     def GE(n, x):
         return integrators.coarse(alg, kind, A, x, t[n + 1], t[n], coarse_steps)
 
-    use_learned = [True] * N
-    U = [u0]
-    for n in range(N):
-        g = GL(n, U[n])
-        if not _finite(alg, g):
-            use_learned[n] = False
-            g = GE(n, U[n])
-        U.append(g)
+    def step0(learned_on):
+        use = [learned_on] * N
+        U0 = [u0]
+        for n in range(N):
+            g = GL(n, U0[n]) if learned_on else GE(n, U0[n])
+            if learned_on and not _finite(alg, g):
+                use[n] = False
+                g = GE(n, U0[n])
+            U0.append(g)
+        return U0, use
+
+    learned_on = True
+    U, use_learned = step0(True)
     iterates = [list(U)]
     increments = []
     choices = [list(use_learned)]
-    k = 0
-    while k < max_iter and k < N:
+    total = 0      # iterations run, across a restart
+    k = 0          # iterations since the last Step 0
+    restarts = 0
+    status = "ok"
+    while total < max_iter and k < N:
         F_k = [F(n, U[n]) for n in range(N)]
         G_old = []
         for n in range(N):
-            gl = GL(n, U[n])
             ge = GE(n, U[n])
-            dl = alg.fro(gl - F_k[n]) if _finite(alg, gl) else np.inf
-            de = alg.fro(ge - F_k[n])
-            use_learned[n] = bool(dl <= de)
+            if learned_on:
+                gl = GL(n, U[n])
+                dl = alg.fro(gl - F_k[n]) if _finite(alg, gl) else np.inf
+                de = alg.fro(ge - F_k[n])
+                use_learned[n] = bool(dl <= de)
+            else:
+                use_learned[n] = False
             G_old.append(gl if use_learned[n] else ge)
         U_new = [u0]
         for n in range(N):
@@ -189,13 +220,30 @@ def parareal_learned(alg, kind, A, u0, T, N, coarse_steps, fine_steps,
         for n in range(1, N + 1):
             d = alg.fro(U_new[n] - U[n])
             s = alg.fro(U_new[n])
-            inc = max(inc, d / s if s > 0 else d)
-        U = U_new
+            q = d / s if s > 0 else d
+            inc = q if q != q else max(inc, q)
+        total += 1
         k += 1
-        iterates.append(list(U))
         increments.append(inc)
         choices.append(list(use_learned))
+        if inc != inc or not all(_finite(alg, x) for x in U_new):
+            if learned_on and total < max_iter:
+                learned_on = False
+                restarts += 1
+                k = 0
+                U, use_learned = step0(False)
+                iterates.append(list(U))
+                continue
+            U = U_new
+            iterates.append(list(U))
+            status = "nonfinite"
+            break
+        U = U_new
+        iterates.append(list(U))
         if inc <= tol:
             break
-    return {"U": U, "iters": k, "increments": increments, "iterates": iterates,
-            "choices": choices}
+    else:
+        if 0 < max_iter <= total and k < N:
+            status = "max_iter"
+    return {"U": U, "iters": total, "increments": increments, "iterates": iterates,
+            "choices": choices, "restarts": restarts, "status": status}

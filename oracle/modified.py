@@ -19,9 +19,21 @@ Definitions of Sec. 3:
   through the coarse propagator instead.  The projection loop of Alg. 2 is
   run twice for every block: the proposition after Alg. 2 states that the
   result is F-orthonormal, which one Gram-Schmidt pass does not deliver in
-  FP64 on these nearly dependent iterates (one pass left the converged
-  modified iterate 3e-8 away from the serial fine solution, two passes 1e-12
-  on the same case); the coefficients r_ji are the sums of both passes.
+  FP64 on these nearly dependent iterates: its loss of orthogonality grows
+  like eps / r_ii^2 (measured in the pin: 3e-9 at a relative remainder of
+  5e-7, 4e-6 at 1e-9), while a second pass restores it to rounding level
+  (Kahan's "twice is enough" result for Gram-Schmidt with one
+  reorthogonalisation, B. N. Parlett, The Symmetric Eigenvalue Problem,
+  1980, Sec. 6-9; for classical Gram-Schmidt: L. Giraud, J. Langou and
+  M. Rozloznik, Numer. Math. 101, 2005).  The coefficients r_ji are the sums
+  of both passes.  The drop tolerance: the direction of a kept block is
+  determined only to about eps ||Z_i|| / r_ii by any algorithm (the pin
+  compares with Householder QR of the vectorised blocks: within
+  1000 eps ||Z_i|| / r_ii, measured 1.3e-8 at r_ii = 4.6e-7 ||Z_i||); with
+  1e-7 no kept direction is uncertain beyond ~1e-7, and a dropped remainder
+  (<= 1e-7 of its block) passes through the coarse instead of the fine
+  propagator, an error of 1e-7 times the coarse propagator's one-slice
+  defect.
 * Projection onto span{Q}: P Y = sum_i alpha_i Q_i with (alpha_i) = Q^T <> Y.
 
 Alg. 3 (linear homogeneous U' = B U): Step 0 is the coarse sweep of Alg. 1.
@@ -48,9 +60,11 @@ def diamond(As, Bs, inner):
     return np.array([[inner(a, b) for b in Bs] for a in As])
 
 
-def global_qr(Z, inner, norm, prefix=(), drop_tol=DROP_TOL):
+def global_qr(Z, inner, norm, prefix=(), drop_tol=DROP_TOL, passes=2):
     """Alg. 2 on the blocks Z, continuing an F-orthonormal `prefix` (kept as
-    is: the basis of S^{k-1} is completed, not recomputed).
+    is: the basis of S^{k-1} is completed, not recomputed).  `passes`: how
+    often the projection loop runs per block (2, reading M1; 1 is Alg. 2 as
+    printed, kept for the test that shows why the second pass is needed).
 
     Returns (Q, R, kept): Q = prefix + accepted new blocks; R[j, i] the
     coefficient of Q_j in Z_i (rows for every block of Q); kept[i] tells
@@ -61,7 +75,7 @@ def global_qr(Z, inner, norm, prefix=(), drop_tol=DROP_TOL):
     for z in Z:
         q = z
         r = {}
-        for _ in range(2):                   # reading M1: the projections twice
+        for _ in range(passes):              # reading M1: the projections twice
             for j, qj in enumerate(Q):
                 c = inner(q, qj)
                 r[j] = r.get(j, 0.0) + c

@@ -112,3 +112,70 @@ def test_global_qr_stays_orthonormal_on_krylov_blocks():
     for i, z in enumerate(Z):
         rec = sum(R[j, i] * Q[j] for j in range(len(Q)))
         assert _fro(z - rec) <= 1e-7 * _fro(z) * 10
+
+
+def _krylov_blocks(count=15, step=0.125):
+    n = 24
+    A = inputs.nonsymmetric(n, 61, shift=0.5, spread=0.5)
+    Z = [inputs.perturbed_identity(n, 62, eps=0.3)]
+    for _ in range(count - 1):
+        Z.append(Z[-1] + step * A @ Z[-1])
+    return Z
+
+
+def test_global_qr_against_householder_on_nearly_dependent_blocks():
+    """Independent reference: LAPACK's Householder QR of the vectorised blocks
+    (numpy.linalg.qr).  Its |R_jj| / ||Z_j|| are the relative remainders rho_j
+    (here from 1 down to 1e-14).  Two Gram-Schmidt passes keep the basis
+    F-orthonormal to rounding at every remainder, one pass does not (loss of
+    orthogonality ~ eps / rho^2); every kept direction agrees with
+    Householder's within 1000 eps / rho_j (the conditioning of a nearly
+    dependent block; any algorithm has it); and with the drop tolerance a
+    block is kept exactly when its remainder against the blocks kept before
+    it (Householder QR of those and the block) exceeds 1e-7 of its norm."""
+    Z = _krylov_blocks()
+    M = np.stack([z.ravel() for z in Z], axis=1)
+    q, r = np.linalg.qr(M)
+    rho = np.abs(np.diag(r)) / np.linalg.norm(M, axis=0)
+    assert rho[0] == 1.0 or abs(rho[0] - 1.0) < 1e-15
+    assert rho.min() < 1e-12 and rho[rho > 1e-7].size >= 5
+    # no remainder near the tolerance (the flags below are then unambiguous)
+    assert np.all(np.abs(np.log10(rho / modified.DROP_TOL)) > 0.3)
+    eps = np.finfo(float).eps
+
+    Q2, R2, kept2 = modified.global_qr(Z, _inner, _fro, drop_tol=0.0)
+    assert all(kept2)
+    D2 = modified.diamond(Q2, Q2, _inner)
+    assert np.abs(D2 - np.eye(len(Q2))).max() < 1e-14
+    Q1, _, _ = modified.global_qr(Z, _inner, _fro, drop_tol=0.0, passes=1)
+    D1 = modified.diamond(Q1, Q1, _inner)
+    assert np.abs(D1 - np.eye(len(Q1))).max() > 1e-6        # one pass is not enough
+    for j in range(len(Z)):
+        if rho[j] < 1e-11:
+            continue                                         # direction is rounding there
+        qj = q[:, j]
+        e = min(_fro(Q2[j].ravel() - qj), _fro(Q2[j].ravel() + qj))
+        assert e <= 1000 * eps / rho[j], (j, e, rho[j])
+        if rho[j] > modified.DROP_TOL:
+            assert e <= 1e-7
+
+    # the drop rule on a shorter sequence whose remainders (against the
+    # blocks kept before) stay clear of the tolerance: 1 .. 8e-9, one block
+    # dropped between two kept ones
+    Z = _krylov_blocks(9, 0.14)
+    Q, R, kept = modified.global_qr(Z, _inner, _fro)
+    ref, acc = [], []
+    for z in Z:
+        Mz = np.stack([Z[i].ravel() for i in acc] + [z.ravel()], axis=1)
+        rz = np.linalg.qr(Mz, mode="r")
+        rem = abs(rz[-1, -1]) / _fro(z)
+        assert abs(np.log10(rem / modified.DROP_TOL)) > 0.3     # unambiguous
+        ref.append(bool(rem > modified.DROP_TOL))
+        if ref[-1]:
+            acc.append(len(ref) - 1)
+    assert kept == ref and kept[6] is False and kept[7] is True and sum(kept) == 7
+    assert np.abs(modified.diamond(Q, Q, _inner) - np.eye(len(Q))).max() < 1e-14
+    # every block is reproduced to within its dropped remainder
+    for i, z in enumerate(Z):
+        rec = sum(R[j, i] * Q[j] for j in range(len(Q)))
+        assert _fro(z - rec) <= (modified.DROP_TOL if not kept[i] else 1e-13) * _fro(z)
