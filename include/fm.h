@@ -192,7 +192,8 @@ typedef struct {
  * Tile shapes and graphs never change results; the padded order can change
  * them at rounding level only (the summation order of norms and dot products).
  * out: host; receives the handle.  Returns FM_ERR_INVALID for batch < 1,
- * n out of range, lda < n, an unknown kind/dtype or a NULL A.
+ * n out of range, lda < n, an unknown kind/dtype or a NULL A, and
+ * FM_ERR_NONFINITE when an A holds an Inf or NaN entry (nothing is created).
  */
 fm_status fm_flow_create(fm_flow* out, const fm_problem* problems, int32_t batch,
                          int32_t dtype, const char* options, void* hip_stream);

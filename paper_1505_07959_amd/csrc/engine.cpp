@@ -509,6 +509,26 @@ fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char*
       if (coarse64) FM_TRY(ensure_b64(i, st));
     }
   }
+  // a non-finite entry of A makes every iterate non-finite: refuse it here
+  {
+    constexpr int blk = 16;
+    FM_TRY(ensure_part((size_t)nb * (blk + 1)));
+    FM_TRY(ensure_hredu((size_t)nb));
+    std::vector<DotItem> it;
+    for (int i = 0; i < nb; ++i)
+      it.push_back(DotItem{inst[i].A64, inst[i].A64, (int64_t)inst[i].np * inst[i].np, i, 1, nullptr});
+    void* d = nullptr;
+    FM_TRY(push(it.data(), it.size() * sizeof(DotItem), &d, st));
+    FM_HIP(launch_dots((const DotItem*)d, nb, part, blk, part + (size_t)nb * blk, st));
+    FM_HIP(hipMemcpyAsync(hredu, part + (size_t)nb * blk, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    FM_HIP(hipStreamSynchronize(st));
+    ring.reset();
+    for (int i = 0; i < nb; ++i)
+      if (hredu[i] != 0.0) {
+        set_error("problem %d: A has %.0f non-finite entries", i, hredu[i]);
+        return FM_ERR_NONFINITE;
+      }
+  }
   if (kv.count("coarse_model")) FM_TRY(load_model(kv["coarse_model"]));
   FM_HIP(hipStreamSynchronize(st));
   return FM_OK;

@@ -23,3 +23,11 @@ def rel(a, b):
 
 def say(msg):
     print(msg, flush=True)
+
+
+def increments_agree(gpu, ref, rtol=1e-6, atol=1e-14):
+    """Parareal increments are norms of differences of computed iterates:
+    they agree to `rtol` relative, or to the rounding of the iterates."""
+    assert len(gpu) == len(ref), (len(gpu), len(ref))
+    for a, b in zip(gpu, ref):
+        assert abs(a - b) <= max(rtol * abs(b), atol), (a, b)

@@ -1,8 +1,9 @@
 """Edge cases of the parareal driver on the GPU against the oracle: the
 smallest orders (1 x 1 and one element past a 64-wide tile), one slice, zero
 iterations, an immediately satisfied tolerance, more iterations requested
-than slices, a start value given by the caller, and a homotopy whose path
-A(t) becomes singular (the library must report FM_ERR_NONFINITE)."""
+than slices, a start value given by the caller, a homotopy whose path
+A(t) becomes singular, and an A with a NaN or Inf entry (the library must
+report FM_ERR_NONFINITE for both)."""
 
 import numpy as np
 import pytest
@@ -90,3 +91,20 @@ def test_singular_homotopy_path_is_reported():
     with pytest.raises(fm.FmError) as ei:
         _solve(HOMOTOPY, A, {"T": 1.0, "N": 8, "fine_steps": 16, "max_iter": 8, "tol": 0.0})
     assert ei.value.status == fm.FM_ERR_NONFINITE
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite_matrix_is_refused(bad):
+    """An Inf or NaN entry in A (of any problem of a batch) is refused at flow
+    creation with FM_ERR_NONFINITE, for every flow kind."""
+    from paper_1505_07959_amd import fm
+    n = 33
+    A, Q, lam = inputs.spd(n, "uniform", 0.5, 2.0, 99)
+    B = A.copy()
+    B[5, 17] = bad
+    for kind in (fm.FM_FLOW_INV_HOMOTOPY, fm.FM_FLOW_INV_STEADY, fm.FM_FLOW_SQRT_STEADY):
+        with pytest.raises(fm.FmError) as ei:
+            fm.fm_flow_create([(kind, dev(A)), (kind, dev(B))], "f64")
+        assert ei.value.status == fm.FM_ERR_NONFINITE and "problem 1" in fm.fm_last_error()
+    h = fm.fm_flow_create([(fm.FM_FLOW_INV_HOMOTOPY, dev(A))], "f64")     # the finite one is accepted
+    fm.fm_destroy(h)

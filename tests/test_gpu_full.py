@@ -1,38 +1,31 @@
 """Full-size parity: each workload at its real size and launch configuration,
-with a bounded iteration count so every test stays well under two minutes.
-Reference: the spectral FP64 oracle of the same discrete method (exact for
-symmetric A with X0 = I), on sampled entries Q diag(x) Q^T[r, c], and the
-exact f(A) after refinement."""
+run to the iteration count its oracle converges in, compared element by
+element.  Reference: the spectral FP64 oracle of the same discrete method
+(exact for symmetric A with X0 = I), formed as the whole matrix
+Q diag(x) Q^T on the host, and the exact f(A) after refinement."""
 
 import os
+import time
 
 import numpy as np
 import pytest
 import torch
 
-from oracle import SpectralAlgebra, HOMOTOPY, STEADY_INV, SQRT, integrators, parareal
+from oracle import SpectralAlgebra, HOMOTOPY, STEADY_INV, SQRT, integrators, parareal, learned, mlp
 from paper_1505_07959_amd import inputs
-from tests.gpu_util import dev, host, empty, rel, say
+from tests.gpu_util import dev, host, empty, rel, say, increments_agree
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 MODELS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1505_07959_amd", "models")
 
 
-def _spectral_parareal(kind, T, Q, lam, N, S, C, K):
+def _spectral_parareal(kind, T, Q, lam, N, S, C, K, tol=0.0):
     alg = SpectralAlgebra(Q, lam)
     t = [i * T / N for i in range(N + 1)]
     F = lambda i, x: integrators.fine(alg, kind, lam, x, t[i + 1], t[i], S)
     G = lambda i, x: integrators.coarse(alg, kind, lam, x, t[i + 1], t[i], C)
-    return alg, parareal.parareal(F, G, alg.eye(), N, K, 0.0, alg.fro)
-
-
-def _samples(n, m=400, seed=0):
-    rng = np.random.default_rng(seed)
-    rows = rng.integers(0, n, m)
-    cols = rng.integers(0, n, m)
-    rows[:50] = cols[:50]          # include diagonal entries
-    return rows, cols
+    return alg, parareal.parareal(F, G, alg.eye(), N, K, tol, alg.fro)
 
 
 def _solve(kind, A, dtype, prm, options=None):
@@ -48,73 +41,164 @@ def _solve(kind, A, dtype, prm, options=None):
         fm.fm_destroy(flow)
 
 
-def _sample(out, rows, cols):
-    return out[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()].cpu().numpy()
+def _compare(out, ref):
+    """Relative Frobenius error and max-abs error relative to max |ref| of
+    the whole matrix."""
+    X = host(out) if isinstance(out, torch.Tensor) else out
+    D = X - ref
+    return float(np.linalg.norm(D) / np.linalg.norm(ref)), float(np.abs(D).max() / np.abs(ref).max())
 
 
-@pytest.mark.parametrize("dtype,bar,K", [("f64", 1e-10, 1), ("f32", 1e-5, 1)])
-def test_large_homotopy_full_size(dtype, bar, K):
-    """n = 4096, N = 64, 16 RK4 steps per slice (the benchmark launch), K iterations."""
-    n, N, S = 4096, 64, 16
+def test_large_homotopy_fp64_converged():
+    """n = 4096, N = 64, 16 RK4 steps per slice (the benchmark launch), FP64,
+    to increment 1e-8: the same iteration count and increment history as the
+    oracle, and the whole final matrix within 1e-10 of the oracle's."""
+    n, N, S, tol = 4096, 64, 16, 1e-8
     A, Q, lam = inputs.large_problem(n)
-    say("large homotopy %s K=%d" % (dtype, K))
-    st, s, out = _solve(HOMOTOPY, A, dtype, {"T": 1.0, "N": N, "fine_steps": S, "max_iter": K, "tol": 0.0})
+    say("large homotopy f64 to tol %g" % tol)
+    st, s, out = _solve(HOMOTOPY, A, "f64", {"T": 1.0, "N": N, "fine_steps": S, "max_iter": N, "tol": tol})
+    alg, ref = _spectral_parareal(HOMOTOPY, 1.0, Q, lam, N, S, 1, N, tol)
+    e, emax = _compare(out, alg.to_matrix(ref["U"][-1]))
+    say("  iters %d (oracle %d), rel err %.2e, max-abs %.2e" % (s["iters"], ref["iters"], e, emax))
+    assert st == 0 and s["iters"] == ref["iters"] == 9
+    increments_agree(s["hist"], ref["increments"])
+    assert e <= 1e-10 and emax <= 1e-10
+
+
+def test_large_homotopy_fp32_converged_iterate():
+    """The same problem with FP32 products and the FP64 correction, run for
+    the oracle's converged iteration count (9): the whole matrix within 1e-5
+    of the oracle's FP64 result (FP32 products converge to the FP32 fine
+    solution, 1.8e-6 away)."""
+    n, N, S, K = 4096, 64, 16, 9
+    A, Q, lam = inputs.large_problem(n)
+    say("large homotopy f32, %d iterations" % K)
+    st, s, out = _solve(HOMOTOPY, A, "f32", {"T": 1.0, "N": N, "fine_steps": S, "max_iter": K, "tol": 0.0})
     alg, ref = _spectral_parareal(HOMOTOPY, 1.0, Q, lam, N, S, 1, K)
-    rows, cols = _samples(n)
-    e = rel(_sample(out, rows, cols), alg.entries(ref["U"][-1], rows, cols))
-    say("  iters %d, sampled rel err %.2e, increment %.3e (oracle %.3e)" %
-        (s["iters"], e, s["hist"][0], ref["increments"][0]))
-    assert s["iters"] == K and e <= bar
-    # the increment is a norm of differences of computed iterates: FP64 to 1e-6
-    # relative, FP32 to the rounding of its products
-    assert abs(s["hist"][0] - ref["increments"][0]) <= (1e-6 if dtype == "f64" else 1e-4) * ref["increments"][0]
+    e, emax = _compare(out, alg.to_matrix(ref["U"][-1]))
+    say("  rel err %.2e, max-abs %.2e, last increment %.2e" % (e, emax, s["hist"][K - 1]))
+    assert s["iters"] == K and e <= 1e-5 and emax <= 1e-5
 
 
 def test_steady_fp16_full_size():
     """n = 8192 X' = X - X A X, N = 32 over [0, 30], 16 RK4 steps per slice,
-    FP16 products: before refinement within the FP16 bar of the oracle's
-    discrete solution; after FP64 Newton-Schulz within 1e-10 of A^{-1}."""
-    n, N, S, T = 8192, 32, 16, 30.0
+    FP16 products, Euler coarse, 3 iterations: before refinement within the
+    FP16 bar of the oracle's discrete solution; after FP64 Newton-Schulz within
+    1e-10 of A^{-1}."""
+    n, N, S, T, K = 8192, 32, 16, 30.0, 3
     A, Q, lam = inputs.steady_problem(n)
-    rows, cols = _samples(n)
-    st, s, out = _solve(STEADY_INV, A, "f16", {"T": T, "N": N, "fine_steps": S, "max_iter": 1, "tol": 0.0})
-    alg, ref = _spectral_parareal(STEADY_INV, T, Q, lam, N, S, 1, 1)
-    e_pre = rel(_sample(out, rows, cols), alg.entries(ref["U"][-1], rows, cols))
-    st, s2, out2 = _solve(STEADY_INV, A, "f16", {"T": T, "N": N, "fine_steps": S, "max_iter": 1, "tol": 0.0,
-                                                  "max_refine": 6, "refine_tol": 1e-13})
-    e_post = rel(_sample(out2, rows, cols), alg.entries(1.0 / lam, rows, cols))
-    say("steady fp16: pre-refinement %.2e, after %d Newton-Schulz steps %.2e (residual %.1e -> %.1e)" %
-        (e_pre, s2["refine_steps"], e_post, s2["residual_before"], s2["residual"]))
+    st, s, out = _solve(STEADY_INV, A, "f16", {"T": T, "N": N, "fine_steps": S, "max_iter": K, "tol": 0.0,
+                                               "max_refine": 6, "refine_tol": 1e-13})
+    alg, ref = _spectral_parareal(STEADY_INV, T, Q, lam, N, S, 1, K)
+    # the pre-refinement iterate: the same solve without refinement
+    st0, s0, out0 = _solve(STEADY_INV, A, "f16", {"T": T, "N": N, "fine_steps": S, "max_iter": K, "tol": 0.0})
+    e_pre, _ = _compare(out0, alg.to_matrix(ref["U"][-1]))
+    del out0
+    e_post, emax = _compare(out, alg.to_matrix(1.0 / lam))
+    say("steady fp16: pre-refinement %.2e, after %d Newton-Schulz steps %.2e (max-abs %.2e; residual %.1e -> %.1e)" %
+        (e_pre, s["refine_steps"], e_post, emax, s["residual_before"], s["residual"]))
     assert e_pre <= 1e-2
     assert e_post <= 1e-10
 
 
-def test_batched_full_size():
-    """All 512 batched problems (n up to 512, BF16 products, two iterations):
-    every problem's iterate against its oracle, then refinement to 1e-10."""
+@pytest.mark.skipif(not os.path.exists(os.path.join(MODELS, "steady_n256.fmw")), reason="no trained model")
+def test_steady_fp16_learned_restarts_like_the_oracle():
+    """The steady workload with the learned coarse step and its Euler
+    fallback.  The polynomial step family is not stable on X - X A X at this
+    slice length (h = 30/32): the FP64 oracle's first sweep already overflows,
+    so the method restarts from Step 0 with Euler.  The library must do the
+    same (one restart, the failed iteration counted), then match the
+    oracle's Euler iterates to the FP16 bar, and refine to 1e-10."""
+    from paper_1505_07959_amd import fm, train_coarse
+    path = os.path.join(MODELS, "steady_n256.fmw")
+    kind, theta, norm = train_coarse.read_model(path)
+    n, N, S, T, K = 8192, 32, 16, 30.0, 4
+    A, Q, lam = inputs.steady_problem(n)
+    mu = [np.mean((lam - 1) ** j) for j in (1, 2, 3, 4)]
+
+    def coeff(t, h):
+        z = (np.array([[t, h] + mu]) - norm[:6]) / norm[6:]
+        return learned.euler_coeffs(STEADY_INV, h) + mlp.forward(theta, z)[0][0]
+
+    alg = SpectralAlgebra(Q, lam)
+    with np.errstate(all="ignore"):
+        ref = learned.parareal_learned(alg, STEADY_INV, lam, alg.eye(), T, N, 1, S, K, 0.0, coeff)
+    assert ref["restarts"] == 1 and ref["iters"] == K
+    prm = {"T": T, "N": N, "fine_steps": S, "max_iter": K, "tol": 0.0, "coarse": fm.FM_COARSE_LEARNED}
+    st0, s0, out0 = _solve(STEADY_INV, A, "f16", prm, "coarse_model=" + path)
+    e_pre, _ = _compare(out0, alg.to_matrix(ref["U"][-1]))
+    del out0
+    st, s, out = _solve(STEADY_INV, A, "f16", dict(prm, max_refine=6, refine_tol=1e-13), "coarse_model=" + path)
+    e_post, _ = _compare(out, alg.to_matrix(1.0 / lam))
+    say("steady fp16 learned: restarts %d (oracle %d), iters %d, pre-refinement %.2e, after refinement %.2e" %
+        (s0["learned_restarts"], ref["restarts"], s0["iters"], e_pre, e_post))
+    assert s0["learned_restarts"] == 1 and s0["iters"] == K and st0 == fm.FM_WARN_NOT_CONVERGED
+    assert e_pre <= 1e-2 and e_post <= 1e-10
+
+
+def _spectral_batch(cases, N, S, C, K):
+    """The spectral oracle for many problems of one kind at once: their
+    eigenvalues side by side in one vector (every operation of the method on
+    X0 = I is elementwise there; with tol = 0 the per-problem norms are not
+    used).  Returns each problem's U^K_N eigenvalues."""
+    lam = np.concatenate([c[4] for c in cases])
+    kind, T = cases[0][0], cases[0][1]
+    _, ref = _spectral_parareal(kind, T, np.zeros((1, 1)), lam, N, S, C, K)
+    out, o = [], 0
+    for c in cases:
+        m = c[4].shape[0]
+        out.append(ref["U"][-1][o:o + m])
+        o += m
+    return out
+
+
+def test_batched_full_size_per_half():
+    """All 512 batched problems (n up to 512), N = 64, 8 RK4 steps per slice,
+    6 iterations, in one persistent launch per product for each half: the
+    inverse half in split BF16 (plain BF16 misses the 1e-2 bar there), the
+    root half in BF16.  Every problem's pre-refinement iterate is within 1e-2
+    of its oracle (whole matrix), and after FP64 refinement within 1e-10 of
+    the exact f(A)."""
     from paper_1505_07959_amd import fm
     cases = [inputs.batched_instance(i) for i in range(512)]
-    K = 2
-    prm = [{"T": T, "N": 64, "fine_steps": 8, "coarse_steps": 1 if k == HOMOTOPY else 2, "max_iter": K,
-            "tol": 0.0, "max_refine": 6, "refine_tol": 1e-13} for k, T, *_ in cases]
-    flow = fm.fm_flow_create([(k, dev(A)) for k, T, A, Q, lam in cases], "bf16")
-    try:
-        outs = [empty(c[2].shape[0]) for c in cases]
-        st, stats = fm.fm_parareal_solve(flow, None, outs, prm)
-        torch.cuda.synchronize()
-        worst = {HOMOTOPY: 0.0, SQRT: 0.0}
-        for j, (kind, T, A, Q, lam) in enumerate(cases):
-            n = A.shape[0]
-            rows, cols = _samples(n, 64, seed=j)
-            f = 1.0 / lam if kind == HOMOTOPY else np.sqrt(lam)
+    K = 6
+    halves = {HOMOTOPY: ("bf16x3", 1), SQRT: ("bf16", 2)}
+    for kind, (dtype, C) in halves.items():
+        sub = [c for c in cases if c[0] == kind]
+        ref = _spectral_batch(sub, 64, 8, C, K)
+        prm = [{"T": T, "N": 64, "fine_steps": 8, "coarse_steps": C, "max_iter": K, "tol": 0.0}
+               for k, T, *_ in sub]
+        flow = fm.fm_flow_create([(k, dev(A)) for k, T, A, Q, lam in sub], dtype)
+        try:
+            outs = [empty(c[2].shape[0]) for c in sub]
+            fm.fm_parareal_solve(flow, None, outs, prm)
+            pre = [host(o) for o in outs]
+            st, stats = fm.fm_parareal_solve(flow, None, outs,
+                                             [dict(p, max_refine=6, refine_tol=1e-13) for p in prm])
+            post = [host(o) for o in outs]
+        finally:
+            fm.fm_destroy(flow)
+        e_pre = e_post = 0.0
+        for j, (k, T, A, Q, lam) in enumerate(sub):
             alg = SpectralAlgebra(Q, lam)
-            e = rel(_sample(outs[j], rows, cols), alg.entries(f, rows, cols))
-            worst[kind] = max(worst[kind], e)
+            e_pre = max(e_pre, rel(pre[j], alg.to_matrix(ref[j])))
+            f = 1.0 / lam if kind == HOMOTOPY else np.sqrt(lam)
+            e_post = max(e_post, rel(post[j], alg.to_matrix(f)))
             assert stats[j]["iters"] == K
-        say("batched 512: worst error after refinement: inverse %.2e, root %.2e" % (worst[HOMOTOPY], worst[SQRT]))
-        assert max(worst.values()) <= 1e-10
-    finally:
-        fm.fm_destroy(flow)
+        say("batched %s half (%d problems, %s): worst pre-refinement %.2e, after refinement %.2e" %
+            ("inverse" if kind == HOMOTOPY else "root", len(sub), dtype, e_pre, e_post))
+        assert e_pre <= 1e-2 and e_post <= 1e-10
+
+
+def _homotopy_coeff_fn(lam):
+    from paper_1505_07959_amd import train_coarse
+    kind, theta, norm = train_coarse.read_model(os.path.join(MODELS, "homotopy_n256.fmw"))
+    mu = [np.mean((lam - 1) ** j) for j in (1, 2, 3, 4)]
+
+    def coeff(t, h):
+        z = (np.array([[t, h] + mu]) - norm[:6]) / norm[6:]
+        return learned.euler_coeffs(HOMOTOPY, h) + mlp.forward(theta, z)[0][0]
+    return coeff
 
 
 @pytest.mark.skipif(not os.path.exists(os.path.join(MODELS, "homotopy_n256.fmw")), reason="no trained model")
@@ -122,44 +206,91 @@ def test_learned_full_size():
     """n = 2048, N = 128, 8 RK4 steps per slice, FP64, learned coarse step with
     the trained network: the first two iterations agree with the oracle run
     with the same per-slice coefficients (taken from the library's network
-    through the oracle's FP64 forward pass) to the FP32 network precision."""
-    from paper_1505_07959_amd import fm, train_coarse
-    from oracle import learned, mlp
-    kind, theta, norm = train_coarse.read_model(os.path.join(MODELS, "homotopy_n256.fmw"))
+    through the oracle's FP64 forward pass) to the FP32 network precision,
+    over the whole matrix."""
+    from paper_1505_07959_amd import fm
     n, N, S, K = 2048, 128, 8, 2
     A, Q, lam = inputs.learned_eval_problem(n)
     st, s, out = _solve(HOMOTOPY, A, "f64", {"T": 1.0, "N": N, "fine_steps": S, "max_iter": K, "tol": 0.0,
                                               "coarse": fm.FM_COARSE_LEARNED},
                         "coarse_model=" + os.path.join(MODELS, "homotopy_n256.fmw"))
-    mu = [np.mean((lam - 1) ** j) for j in (1, 2, 3, 4)]
-
-    def coeff(t, h):
-        z = (np.array([[t, h] + mu]) - norm[:6]) / norm[6:]
-        return learned.euler_coeffs(HOMOTOPY, h) + mlp.forward(theta, z)[0][0]
-
     alg = SpectralAlgebra(Q, lam)
-    ref = learned.parareal_learned(alg, HOMOTOPY, lam, alg.eye(), 1.0, N, 1, S, K, 0.0, coeff)
-    rows, cols = _samples(n)
-    e = rel(_sample(out, rows, cols), alg.entries(ref["U"][-1], rows, cols))
-    say("learned n=2048: iters %d, sampled rel err vs oracle %.2e" % (s["iters"], e))
+    ref = learned.parareal_learned(alg, HOMOTOPY, lam, alg.eye(), 1.0, N, 1, S, K, 0.0, _homotopy_coeff_fn(lam))
+    e, emax = _compare(out, alg.to_matrix(ref["U"][-1]))
+    say("learned n=2048: iters %d, rel err vs oracle %.2e (max-abs %.2e), learned slices %d (oracle %d)" %
+        (s["iters"], e, emax, s["learned_slices"], sum(ref["choices"][-1])))
     assert s["learned_restarts"] == 0
     assert e <= 1e-5
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(MODELS, "homotopy_n256.fmw")), reason="no trained model")
+def test_learned_beats_euler_to_1e8():
+    """The learned coarse step's gain: the inverse homotopy at n = 2048
+    (lam ~ loguniform[1e-2, 10]), N = 128 slices, 8 RK4 steps per slice, FP64
+    products, increment tolerance 1e-8.  With the trained network parareal
+    takes fewer iterations and less wall time than with the Euler step, with
+    no restart; both reach the same fixed point (the serial fine solution,
+    computed by the same kernels) to 1e-8; the oracle, run with the same
+    coefficients, predicts the iteration counts.  (With FP32 products neither
+    coarse step reaches 1e-8: the FP32 increment floors sit near 5e-8.)"""
+    from paper_1505_07959_amd import fm
+    n, N, S, tol = 2048, 128, 8, 1e-8
+    A, Q, lam = inputs.learned_eval_problem(n)
+    path = os.path.join(MODELS, "homotopy_n256.fmw")
+    flow = fm.fm_flow_create([(HOMOTOPY, dev(A))], "f64", "coarse_model=" + path)
+    res = {}
+    try:
+        out = empty(n)
+        prm = {"T": 1.0, "N": N, "fine_steps": S, "max_iter": N, "tol": tol}
+        fm.fm_parareal_solve(flow, None, [out], [dict(prm, max_iter=1, coarse=fm.FM_COARSE_LEARNED)])  # warm-up
+        for name, coarse in (("euler", fm.FM_COARSE_EULER), ("learned", fm.FM_COARSE_LEARNED)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, stats = fm.fm_parareal_solve(flow, None, [out], [dict(prm, coarse=coarse)])
+            torch.cuda.synchronize()
+            res[name] = (st, stats[0], time.perf_counter() - t0, host(out))
+        X0 = [torch.eye(n, dtype=torch.float64, device="cuda")]
+        Xs = [empty(n)]
+        fm.fm_fine_propagate(flow, 1.0, 0.0, N * S, X0, Xs)
+        ser = host(Xs[0])
+    finally:
+        fm.fm_destroy(flow)
+    alg = SpectralAlgebra(Q, lam)
+    ref_l = learned.parareal_learned(alg, HOMOTOPY, lam, alg.eye(), 1.0, N, 1, S, N, tol, _homotopy_coeff_fn(lam))
+    _, ref_e = _spectral_parareal(HOMOTOPY, 1.0, Q, lam, N, S, 1, N, tol)
+    el, ee = rel(res["learned"][3], ser), rel(res["euler"][3], ser)
+    say("learned vs Euler to 1e-8: iterations %d vs %d (oracle %d vs %d), %.2f s vs %.2f s, "
+        "error vs serial fine %.1e vs %.1e" % (res["learned"][1]["iters"], res["euler"][1]["iters"], ref_l["iters"],
+                                              ref_e["iters"], res["learned"][2], res["euler"][2], el, ee))
+    assert res["learned"][0] == fm.FM_OK and res["euler"][0] == fm.FM_OK
+    assert res["learned"][1]["learned_restarts"] == 0
+    assert res["learned"][1]["iters"] == ref_l["iters"] and res["euler"][1]["iters"] == ref_e["iters"]
+    assert res["learned"][1]["iters"] < res["euler"][1]["iters"]
+    assert res["learned"][2] < res["euler"][2]
+    assert el <= 1e-8 and ee <= 1e-8
 
 
 def test_maximum_order_fp64():
     """The largest order the interface accepts, with a ragged tail: n = 16383
     (padded to 16384), homotopy flow, FP64, N = 2 slices of 2 RK4 steps, one
-    iteration; sampled entries against the spectral oracle (A = Q diag(lam) Q
-    with a Householder reflector Q, formed in O(n^2))."""
+    iteration; the whole matrix against the spectral oracle (A = Q diag(lam) Q
+    with a Householder reflector Q = I - 2 v v^T, so Q diag(x) Q is formed in
+    O(n^2) like A)."""
     n, N, S, K = 16383, 2, 2, 1
     A, Q, lam = inputs.spd_reflector(n, 0.3, 2.0, 77)
     say("maximum order n=%d" % n)
     st, s, out = _solve(HOMOTOPY, A, "f64", {"T": 1.0, "N": N, "fine_steps": S, "max_iter": K, "tol": 0.0})
     del A
     alg, ref = _spectral_parareal(HOMOTOPY, 1.0, Q, lam, N, S, 1, K)
-    rows, cols = _samples(n)
-    rows[-20:] = n - 1                      # the last row and column (next to the padding)
-    cols[-10:] = n - 1
-    e = rel(_sample(out, rows, cols), alg.entries(ref["U"][-1], rows, cols))
-    say("  iters %d, sampled rel err %.2e" % (s["iters"], e))
-    assert s["iters"] == K and e <= 1e-10
+    j = int(np.argmin(np.diag(Q)))                  # largest |v_j|
+    v = (np.eye(1, n, j).ravel() - Q[:, j]) / np.sqrt(2.0 * (1.0 - Q[j, j]))
+    del Q
+    x = ref["U"][-1]
+    w = x * v
+    R = -2.0 * (np.outer(v, w) + np.outer(w, v))
+    R += (4.0 * float(v @ w)) * np.outer(v, v)
+    R[np.diag_indices(n)] += x
+    e, emax = _compare(out, R)
+    say("  iters %d, rel err %.2e, max-abs %.2e (last row %.2e)" %
+        (s["iters"], e, emax, rel(host(out[-1]), R[-1])))
+    assert s["iters"] == K and e <= 1e-10 and emax <= 1e-10
