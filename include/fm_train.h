@@ -47,7 +47,8 @@ fm_status fm_mlp_loss(const float* Y, const float* cbase, const double* G, const
 
 /* grad (9288) = d(sum_s L_s / S)/d theta by back-propagation of dY through the
  * network evaluated by fm_mlp_forward (its X and acts); deltas: scratch
- * S x 192. */
+ * S x 192.  The sample sums run in 32 parallel classes whose partial sums sit
+ * in a fixed device array of the library: calls on one GPU must not overlap. */
 fm_status fm_mlp_backward(const float* theta, const float* norm, const float* X, const float* acts,
                           const float* dY, int64_t S, float* deltas, float* grad, void* hip_stream);
 

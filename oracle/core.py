@@ -47,6 +47,10 @@ class MatrixAlgebra:
         """Frobenius inner product <X, Y>_F = tr(Y^T X) (Sec. 3)."""
         return float(np.sum(X * Y))
 
+    def solve(self, M, B):
+        """M^{-1} B by LU with partial pivoting (LAPACK gesv)."""
+        return np.linalg.solve(M, B)
+
     def trace(self, X):
         return float(np.trace(X))
 
@@ -75,6 +79,9 @@ class SpectralAlgebra:
 
     def inner(self, X, Y):
         return float(np.sum(X * Y))
+
+    def solve(self, M, B):
+        return B / M
 
     def trace(self, X):
         return float(np.sum(X))

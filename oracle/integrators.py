@@ -10,15 +10,23 @@ F(T_{n+1}, T_n, x), both mapping a value at T_n to one at T_{n+1}.
       k1 = F(X), k2 = F(X + h/2 k1), k3 = F(X + h/2 k2), k4 = F(X + h k3),
       X <- X + h/6 (k1 + 2 k2 + 2 k3 + k4).
 * Coarse G: `steps` forward-Euler steps X <- X + h F(X).
+* Crank-Nicolson (Sec. 2, Example 2 computes exp(B) with Crank-Nicolson
+  coarse and fine propagators), for the linear flows F(X) = s A X + b I
+  (EXP: s = 1, b = 0; INV_LINEAR: s = -1, b = 1): the trapezoidal rule
+  X+ - X = h/2 (F(X+) + F(X)), i.e. one linear solve per step,
+      (I - s h/2 A) X+ = (I + s h/2 A) X + h b I.
 
 The flows are autonomous, so only the step size depends on the times.
 
-Parity: pinned by convergence order (RK4 error ratio 16, Euler ratio 2 when h
-halves) against the closed forms in ``exact`` (tests/test_oracle_flows.py).
+Parity: pinned by convergence order (RK4 error ratio 16, Euler ratio 2,
+Crank-Nicolson ratio 4 when h halves) against the closed forms in ``exact``;
+Crank-Nicolson also by its scalar form, the (1,1) Pade approximant
+(1 + z/2) / (1 - z/2) of e^z, and by keeping the steady state A^{-1} of
+INV_LINEAR fixed (tests/test_oracle_flows.py).
 """
 
 from .flows import rhs, shifted
-from .core import HOMOTOPY
+from .core import HOMOTOPY, EXP, INV_LINEAR
 
 
 def rk4_step(alg, kind, X, A, h, M=None):
@@ -62,3 +70,30 @@ def serial_fine(alg, kind, A, X0, T, N, steps):
     for n in range(N):
         out.append(fine(alg, kind, A, out[-1], (n + 1) * T / N, n * T / N, steps))
     return out
+
+
+def _linear_coeffs(kind):
+    if kind == EXP:
+        return 1.0, 0.0
+    if kind == INV_LINEAR:
+        return -1.0, 1.0
+    raise ValueError("Crank-Nicolson is defined here for the linear flows only")
+
+
+def cn_step(alg, kind, X, A, h):
+    """One Crank-Nicolson step: solve (I - s h/2 A) X+ = (I + s h/2 A) X + h b I."""
+    s, b = _linear_coeffs(kind)
+    I = alg.eye()
+    M = I - (s * h / 2) * A
+    rhs_ = X + (s * h / 2) * alg.mul(A, X)
+    if b:
+        rhs_ = rhs_ + (h * b) * I
+    return alg.solve(M, rhs_)
+
+
+def cn(alg, kind, A, X, t_next, t_cur, steps):
+    """`steps` Crank-Nicolson steps from t_cur to t_next (fine or coarse)."""
+    h = (t_next - t_cur) / steps
+    for _ in range(steps):
+        X = cn_step(alg, kind, X, A, h)
+    return X

@@ -6,8 +6,9 @@
 // layers of width 64, linear output of 8; flat weights layer by layer
 // (W out x in row-major, then b).  One thread evaluates one sample with all
 // weights staged in LDS (37 KB, broadcast reads).  Weight gradients are sums
-// over samples, computed one parameter per thread in sample order
-// (deterministic, no atomics).
+// over samples: WG_CH sample classes (s mod WG_CH) are summed in parallel,
+// one parameter per thread in sample order, then the class sums are added
+// in class order (deterministic, no atomics).
 #include "fm_common.h"
 #include "fm_mlp.h"
 
@@ -130,28 +131,38 @@ __global__ __launch_bounds__(MT) void k_mlp_delta(const float* __restrict__ thet
   for (int i = 0; i < NH; ++i) deltas[s * 3 * NH + i] = d[i];
 }
 
-// One thread per parameter: weight gradients as sums over samples.
+// Weight gradients as sums over samples:
 //   layer l: gW[o][i] = sum_s delta_l[s][o] * in_l[s][i], gb[o] = sum_s delta_l[s][o]
 // with in_1 = z (standardised inputs), in_l = h_{l-1}; delta_4 = dY.
-__global__ void k_mlp_wgrad(const float* __restrict__ norm, const float* __restrict__ X,
-                            const float* __restrict__ acts, const float* __restrict__ deltas,
-                            const float* __restrict__ dY, int64_t S, float* __restrict__ grad) {
+// Stage 1, grid (parameter blocks, WG_CH): block (b, c) sums samples
+// s = c, c + WG_CH, ... for its parameters into g_wgrad_part[c][p]; the
+// threads of a block read neighbouring entries of one sample row at a time.
+// Stage 2 adds the WG_CH partial sums of each parameter in class order.
+// The partial sums live in a fixed device array: backward calls on one GPU
+// must not overlap.
+constexpr int WG_CH = 32;
+__device__ double g_wgrad_part[WG_CH * NPARAM];
+
+__global__ __launch_bounds__(256) void k_mlp_wgrad_part(const float* __restrict__ norm, const float* __restrict__ X,
+                                                        const float* __restrict__ acts,
+                                                        const float* __restrict__ deltas,
+                                                        const float* __restrict__ dY, int64_t S) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
   if (p >= NPARAM) return;
-  int layer, o, i, nin;
+  int layer, o, i;
   bool bias;
-  if (p < OFF_B1) { layer = 1; nin = NI; o = p / NI; i = p % NI; bias = false; }
-  else if (p < OFF_W2) { layer = 1; nin = NI; o = p - OFF_B1; i = 0; bias = true; }
-  else if (p < OFF_B2) { layer = 2; nin = NH; o = (p - OFF_W2) / NH; i = (p - OFF_W2) % NH; bias = false; }
-  else if (p < OFF_W3) { layer = 2; nin = NH; o = p - OFF_B2; i = 0; bias = true; }
-  else if (p < OFF_B3) { layer = 3; nin = NH; o = (p - OFF_W3) / NH; i = (p - OFF_W3) % NH; bias = false; }
-  else if (p < OFF_W4) { layer = 3; nin = NH; o = p - OFF_B3; i = 0; bias = true; }
-  else if (p < OFF_B4) { layer = 4; nin = NH; o = (p - OFF_W4) / NH; i = (p - OFF_W4) % NH; bias = false; }
-  else { layer = 4; nin = NH; o = p - OFF_B4; i = 0; bias = true; }
-  (void)nin;
+  if (p < OFF_B1) { layer = 1; o = p / NI; i = p % NI; bias = false; }
+  else if (p < OFF_W2) { layer = 1; o = p - OFF_B1; i = 0; bias = true; }
+  else if (p < OFF_B2) { layer = 2; o = (p - OFF_W2) / NH; i = (p - OFF_W2) % NH; bias = false; }
+  else if (p < OFF_W3) { layer = 2; o = p - OFF_B2; i = 0; bias = true; }
+  else if (p < OFF_B3) { layer = 3; o = (p - OFF_W3) / NH; i = (p - OFF_W3) % NH; bias = false; }
+  else if (p < OFF_W4) { layer = 3; o = p - OFF_B3; i = 0; bias = true; }
+  else if (p < OFF_B4) { layer = 4; o = (p - OFF_W4) / NH; i = (p - OFF_W4) % NH; bias = false; }
+  else { layer = 4; o = p - OFF_B4; i = 0; bias = true; }
   double acc = 0.0;
-  for (int64_t s = 0; s < S; ++s) {
-    float dv = layer == 4 ? dY[s * NO + o] : deltas[s * 3 * NH + (layer - 1) * NH + o];
+  for (int64_t s = c; s < S; s += WG_CH) {
+    const float dv = layer == 4 ? dY[s * NO + o] : deltas[s * 3 * NH + (layer - 1) * NH + o];
     float in = 1.f;
     if (!bias) {
       if (layer == 1) in = (X[s * NI + i] - norm[i]) / norm[NI + i];
@@ -159,6 +170,14 @@ __global__ void k_mlp_wgrad(const float* __restrict__ norm, const float* __restr
     }
     acc += (double)dv * (double)in;
   }
+  g_wgrad_part[(int64_t)c * NPARAM + p] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_wgrad_sum(float* __restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  double acc = 0.0;
+  for (int c = 0; c < WG_CH; ++c) acc += g_wgrad_part[(int64_t)c * NPARAM + p];
   grad[p] = (float)acc;
 }
 
@@ -318,7 +337,11 @@ hipError_t mlp_backward(const float* theta, const float* norm, const float* X, c
   hipLaunchKernelGGL(k_mlp_delta, dim3((S + MT - 1) / MT), dim3(MT), 0, st, theta, acts, dY, S, deltas);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3((NPARAM + 255) / 256), dim3(256), 0, st, norm, X, acts, deltas, dY, S, grad);
+  hipLaunchKernelGGL(k_mlp_wgrad_part, dim3((NPARAM + 255) / 256, WG_CH), dim3(256), 0, st, norm, X, acts, deltas,
+                     dY, S);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_wgrad_sum, dim3((NPARAM + 255) / 256), dim3(256), 0, st, grad);
   return hipGetLastError();
 }
 

@@ -240,3 +240,56 @@ def test_reflector_generator():
     A, Q, lam = inputs.spd_reflector(40, 0.5, 2.0, 3)
     assert np.allclose(Q @ Q, np.eye(40), atol=1e-14)
     assert np.allclose(A, (Q * lam) @ Q, atol=1e-13) and np.array_equal(A, A.T)
+
+
+# ---- Crank-Nicolson (Sec. 2, Example 2) -----------------------------------
+
+@pytest.mark.parametrize("kind", [EXP, INV_LINEAR])
+def test_crank_nicolson_second_order(kind):
+    """Error against the closed form (non-commuting start) falls by 4 when h
+    halves: the trapezoidal rule is second order."""
+    A, _, _, X0 = _problem(6, 31)
+    A = -A if kind == EXP else A
+    alg = MatrixAlgebra(6)
+    T = 0.8
+    errs = []
+    for steps in (8, 16, 32):
+        X = integrators.cn(alg, kind, A, X0, T, 0.0, steps)
+        errs.append(np.linalg.norm(X - exact.closed_form(kind, A, X0, T)))
+    assert 3.8 < errs[0] / errs[1] < 4.2 and 3.8 < errs[1] / errs[2] < 4.2
+
+
+def test_crank_nicolson_is_the_pade_approximant_by_eigenvectors():
+    """On a non-symmetric diagonalisable A, one step of the exponential flow
+    is V diag(r(h lam)) V^{-1} X with r(z) = (1 + z/2) / (1 - z/2), the (1,1)
+    Pade approximant of e^z, evaluated through a complex eigendecomposition
+    (an independent route: no linear solve)."""
+    n = 7
+    A = inputs.nonsymmetric(n, 33, shift=-1.0, spread=0.8)
+    X0 = inputs.perturbed_identity(n, 34, eps=0.3)
+    alg = MatrixAlgebra(n)
+    h = 0.37
+    lam, V = np.linalg.eig(A)
+    r = (1 + h * lam / 2) / (1 - h * lam / 2)
+    ref = (V @ np.diag(r) @ np.linalg.inv(V) @ X0).real
+    got = integrators.cn_step(alg, EXP, X0, A, h)
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+    # the spectral algebra takes the same step on eigenvalues
+    As, Q, lam_s = inputs.spd(n, "uniform", 0.2, 3.0, 35)
+    x = integrators.cn_step(SpectralAlgebra(Q, lam_s), EXP, np.ones(n), lam_s, h)
+    M = integrators.cn_step(alg, EXP, np.eye(n), As, h)
+    assert np.linalg.norm((Q * x) @ Q.T - M) <= 1e-13 * np.linalg.norm(M)
+
+
+def test_crank_nicolson_keeps_the_steady_state():
+    """The inverse A^{-1}, steady state of dX/dt = I - A X, is a fixed point of
+    every Crank-Nicolson step (the trapezoidal rule preserves equilibria of
+    a linear field), whatever the step size; and a long run converges to it."""
+    A, _, _, X0 = _problem(6, 36)
+    alg = MatrixAlgebra(6)
+    Ainv = exact.inverse_lu(A)
+    for h in (0.01, 0.5, 3.0):
+        X = integrators.cn_step(alg, INV_LINEAR, Ainv, A, h)
+        assert np.linalg.norm(X - Ainv) <= 1e-13 * np.linalg.norm(Ainv)
+    X = integrators.cn(alg, INV_LINEAR, A, X0, 60.0, 0.0, 600)
+    assert np.linalg.norm(X - Ainv) <= 1e-10 * np.linalg.norm(Ainv)
