@@ -218,6 +218,30 @@ fm_status fm_fine_propagate(fm_flow f, double t_next, double t_cur, int32_t step
                             const double* const* X_in, double* const* X_out,
                             void* hip_stream);
 
+/* Size in bytes of the fixed device scratch of fm_fine_propagate_noalloc
+ * (one copy per GPU, held for the life of the process). */
+#define FM_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/*
+ * fm_fine_propagate without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same propagation and the same kernels, with
+ * the workspace taken from a fixed device array of FM_NOALLOC_SCRATCH_BYTES
+ * instead of the flow's grown workspace, no graph capture and no timing
+ * events.  The workspace needs, summed over the flow's problems of padded
+ * order np, np^2 (40 bytes for FM_F64, 24 for FM_F32, 18 for FM_BF16/F16
+ * plus 4 for their FP32 state, 28 for FM_BF16X3) rounded up to 256 bytes
+ * per matrix; more returns FM_ERR_INVALID (nothing launched).  The flow
+ * itself (fm_flow_create) is allocated beforehand.  All calls on one GPU
+ * share its one array: calls that overlap on a GPU (concurrent streams,
+ * host threads) race and must be serialised by the caller.  The array holds
+ * the last call's intermediates; every call overwrites what it reads.
+ * Blocks until the item lists are staged, otherwise asynchronous.
+ */
+fm_status fm_fine_propagate_noalloc(fm_flow f, double t_next, double t_cur, int32_t steps,
+                                    const double* const* X_in, double* const* X_out,
+                                    void* hip_stream);
+
 /*
  * Coarse propagator G(t_next, t_cur, X) of Alg. 1: `steps` forward-Euler steps
  * (coarse = FM_COARSE_EULER) or learned polynomial steps (FM_COARSE_LEARNED,

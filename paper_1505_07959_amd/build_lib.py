@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfm.so")
 
-SOURCES = ["gemm.hip", "ew.hip", "mlp.hip", "engine.cpp", "api.cpp"]
+SOURCES = ["gemm.hip", "ew.hip", "mlp.hip", "noalloc.hip", "engine.cpp", "api.cpp"]
 
 ARCH = os.environ.get("FM_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

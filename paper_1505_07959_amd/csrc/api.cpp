@@ -154,6 +154,20 @@ fm_status fm_fine_propagate(fm_flow f, double t_next, double t_cur, int32_t step
   return f->impl.fine_propagate(t_next, t_cur, steps, X_in, X_out, (hipStream_t)hip_stream);
 }
 
+fm_status fm_fine_propagate_noalloc(fm_flow f, double t_next, double t_cur, int32_t steps,
+                                    const double* const* X_in, double* const* X_out, void* hip_stream) {
+  fm::clear_error();
+  fm_status s = check_prop(f, t_next, t_cur, steps, X_in, X_out);
+  if (s != FM_OK) return s;
+  char* ws = fm::noalloc_scratch(f->impl.device);
+  if (!ws) {
+    set_error("the allocation-free scratch of device %d was not set up", f->impl.device);
+    return FM_ERR_DEVICE;
+  }
+  return f->impl.fine_propagate(t_next, t_cur, steps, X_in, X_out, (hipStream_t)hip_stream, ws,
+                                fm::kNoallocScratchBytes);
+}
+
 fm_status fm_coarse_propagate(fm_flow f, double t_next, double t_cur, int32_t steps, int32_t coarse,
                               const double* const* X_in, double* const* X_out, void* hip_stream) {
   fm::clear_error();

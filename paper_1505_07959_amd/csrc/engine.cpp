@@ -463,6 +463,7 @@ static void parse_options(const char* opt, std::map<std::string, std::string>& k
 
 fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char* options, hipStream_t st) {
   FM_HIP(hipGetDevice(&device));
+  FM_TRY(noalloc_setup());
   dt = dtype;
   batch = nb;
   std::map<std::string, std::string> kv;
@@ -631,8 +632,10 @@ static GItem blank_item(const Inst& in, int i) {
 // slot.x; slot.ya must hold op(x) on entry.  One grouped launch per product:
 // stage s reads Y from ya (s odd) or yb (s even) and writes the next stage
 // operand to the other buffer, so after 4 stages Y is back in ya.
-fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int method, hipStream_t st) {
+fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int method, hipStream_t st,
+                         float* x32_ws, bool plain) {
   if (slots.empty() || steps <= 0) return FM_OK;
+  const bool timed = timing && !plain;
   // Build the 8 item lists once; they are identical for every step.
   // RK4: one unit = one step of 4 stages (operands ya -> yb -> ya -> yb -> ya).
   // Forward Euler: one unit = two steps (ya -> yb -> ya); an odd step count
@@ -652,11 +655,12 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
   if (x32) {
     size_t need = 0;
     for (const FineSlot& sl : slots) need += ((size_t)inst[sl.inst].np * inst[sl.inst].np + 63) / 64 * 64;
-    FM_TRY(ensure_x32(need));
+    if (!x32_ws) FM_TRY(ensure_x32(need));
+    float* xbase = x32_ws ? x32_ws : x32buf;
     size_t off = 0;
     for (size_t k = 0; k < slots.size(); ++k) {
       const int64_t np2 = (int64_t)inst[slots[k].inst].np * inst[slots[k].inst].np;
-      xs[k] = x32buf + off;
+      xs[k] = xbase + off;
       off += ((size_t)np2 + 63) / 64 * 64;
       narrow.push_back(CastItem{slots[k].x, xs[k], np2, 1, 0});
       widen.push_back(CastItem{xs[k], slots[k].x, np2, 0, 0});
@@ -769,7 +773,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
     if (s == 0) first_stage_end = seq.size();
   }
   int phase_ev = -1;
-  if (timing) {
+  if (timed) {
     phase_ev = (int)ev_used;
     hipEvent_t e0 = next_event(), e1 = next_event();
     if (!e0 || !e1) timing = false;
@@ -783,7 +787,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
       }
     return FM_OK;
   };
-  if (use_graph && cap_stream && units > 1) {
+  if (use_graph && cap_stream && units > 1 && !plain) {
     // capture the launches of one unit once, replay the graph for every unit
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
@@ -809,7 +813,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
     for (const Launch& L : seq) unit_flops += L.flops;
     for (int u = 0; u < units; ++u) {
       int idx = -1;
-      if (timing) {
+      if (timed) {
         idx = (int)ev_used;
         hipEvent_t a = next_event(), b = next_event();
         if (a && b) FM_HIP(hipEventRecord(a, st));
@@ -823,7 +827,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
     }
     FM_TRY(launch_tail());
     FM_TRY(widen_back());
-    if (timing && phase_ev >= 0) {
+    if (timed && phase_ev >= 0) {
       FM_HIP(hipEventRecord(ev[phase_ev + 1], st));
       phase_pairs.push_back(phase_ev);
     }
@@ -831,7 +835,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
   }
   for (int u = 0; u < units; ++u)
     for (const Launch& L : seq) {
-      const bool rec = timing;
+      const bool rec = timed;
       int idx = -1;
       if (rec) {
         idx = (int)ev_used;
@@ -847,7 +851,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
     }
   FM_TRY(launch_tail());
   FM_TRY(widen_back());
-  if (timing && phase_ev >= 0) {
+  if (timed && phase_ev >= 0) {
     FM_HIP(hipEventRecord(ev[phase_ev + 1], st));
     phase_pairs.push_back(phase_ev);
   }
@@ -972,27 +976,55 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
 
 // ------------------------------------------------- standalone propagators
 fm_status Flow::fine_propagate(double t1, double t0, int steps, const double* const* xin, double* const* xout,
-                               hipStream_t st) {
-  // workspace: per problem x (FP64), ya, yb, p (op), kacc (acc)
+                               hipStream_t st, char* ws, size_t ws_cap) {
+  // workspace: per problem x (FP64), ya, yb, p (op), kacc (acc); with a
+  // caller's workspace also the FP32 states of the 16-bit products
+  const bool ext = ws != nullptr;
+  const bool x32 = dt == DT_BF16 || dt == DT_F16 || dt == DT_BF16X3;
+  Arena own;
+  Arena& ar = ext ? own : prop;
   std::vector<FineSlot> slots(batch);
+  float* x32_ws = nullptr;
   for (int pass = 0; pass < 2; ++pass) {
-    prop.measuring = (pass == 0);
-    prop.used = 0;
+    ar.measuring = (pass == 0);
+    ar.used = 0;
     for (int i = 0; i < batch; ++i) {
       const size_t np2 = (size_t)inst[i].np * inst[i].np;
       FineSlot& s = slots[i];
       s.inst = i;
-      s.x = (double*)prop.take(np2 * 8);
-      s.ya = prop.take(np2 * dt_size(dt));
-      s.yb = prop.take(np2 * dt_size(dt));
-      s.p = prop.take(np2 * dt_size(dt));
-      s.kacc = prop.take(np2 * acc_size(dt));
+      s.x = (double*)ar.take(np2 * 8);
+      s.ya = ar.take(np2 * dt_size(dt));
+      s.yb = ar.take(np2 * dt_size(dt));
+      s.p = ar.take(np2 * dt_size(dt));
+      s.kacc = ar.take(np2 * acc_size(dt));
       s.h = (t1 - t0) / steps;
     }
-    if (pass == 0) FM_TRY(prop.reserve(prop.used));
+    if (ext && x32) {
+      size_t need = 0;
+      for (int i = 0; i < batch; ++i) need += ((size_t)inst[i].np * inst[i].np + 63) / 64 * 64;
+      x32_ws = (float*)ar.take(need * sizeof(float));
+    }
+    if (pass == 0) {
+      if (!ext) {
+        FM_TRY(prop.reserve(prop.used));
+      } else {
+        if (ar.used > ws_cap) {
+          set_error("workspace of %zu bytes needed, the allocation-free scratch holds %zu", ar.used, ws_cap);
+          return FM_ERR_INVALID;
+        }
+        own.base = ws;
+        own.cap = ws_cap;
+      }
+    }
   }
   FM_HIP(hipStreamSynchronize(st));
-  release_graphs();
+  if (ext) {
+    // earlier graphs stay alive (destroying them frees memory); only wait
+    // for their streams before the item ring is reused
+    for (auto q : pending_stream) FM_HIP(hipStreamSynchronize(q));
+  } else {
+    release_graphs();
+  }
   ring.reset();
   {
     std::vector<double*> dst(batch);
@@ -1011,7 +1043,7 @@ fm_status Flow::fine_propagate(double t1, double t0, int steps, const double* co
   void* d = nullptr;
   FM_TRY(push(prep.data(), prep.size() * sizeof(PrepItem), &d, st));
   FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), dt, nullptr, st));
-  FM_TRY(run_fine(slots, steps, FM_FINE_RK4, st));
+  FM_TRY(run_fine(slots, steps, FM_FINE_RK4, st, x32_ws, ext));
   {
     std::vector<double*> dst(batch);
     std::vector<const double*> src(batch);

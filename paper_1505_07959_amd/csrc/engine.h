@@ -175,7 +175,11 @@ struct Flow {
                      hipStream_t st);
   fm_status ensure_hredu(size_t count);
 
-  fm_status run_fine(const std::vector<FineSlot>& slots, int steps, int method, hipStream_t st);
+  // plain: no graph capture and no timing events (nothing allocated); x32_ws:
+  // FP32 states of a 16-bit fine solve taken from the caller's workspace
+  // instead of the flow's grown buffer
+  fm_status run_fine(const std::vector<FineSlot>& slots, int steps, int method, hipStream_t st,
+                     float* x32_ws = nullptr, bool plain = false);
   fm_status run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipStream_t st);
   // coefficients for rows (problem, t, h): c = c_Euler(h) + net(t, h, mu)
   struct CoefRow {
@@ -188,8 +192,10 @@ struct Flow {
                      double* fD, double* fn, int64_t row0, hipStream_t st);
   fm_status set_model(int kind, const double* theta, const double* norm);
 
+  // ws == nullptr: workspace from the flow's propagator arena (grown on
+  // demand); else the caller's ws_cap bytes at ws, and nothing is allocated
   fm_status fine_propagate(double t1, double t0, int steps, const double* const* xin, double* const* xout,
-                           hipStream_t st);
+                           hipStream_t st, char* ws = nullptr, size_t ws_cap = 0);
   fm_status coarse_propagate(double t1, double t0, int steps, int coarse, const double* const* xin,
                              double* const* xout, hipStream_t st);
   fm_status double_angle(double* C, int m, hipStream_t st);
@@ -206,5 +212,13 @@ struct Flow {
   GemmCfg pick_cfg(int dt, int np);
   int pick_order(int dt, int n);
 };
+
+// Scratch of the allocation-free entry point (noalloc.hip): a fixed device
+// array per GPU.  noalloc_setup() looks up its address on the current device
+// once (called at flow creation); noalloc_scratch() returns it (null before
+// setup).
+constexpr size_t kNoallocScratchBytes = FM_NOALLOC_SCRATCH_BYTES;
+fm_status noalloc_setup();
+char* noalloc_scratch(int device);
 
 }  // namespace fm

@@ -86,12 +86,14 @@ def _load():
                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(fm_stats), ctypes.c_char_p, P]
     lib.fm_cos.restype = ctypes.c_int
     lib.fm_fine_propagate.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, PP, PP, P]
+    lib.fm_fine_propagate_noalloc.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, PP, PP, P]
     lib.fm_coarse_propagate.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                         PP, PP, P]
     lib.fm_destroy.argtypes = [P]
     lib.fm_destroy.restype = None
     lib.fm_last_error.restype = ctypes.c_char_p
-    for f in ("fm_flow_create", "fm_parareal_solve", "fm_fine_propagate", "fm_coarse_propagate"):
+    for f in ("fm_flow_create", "fm_parareal_solve", "fm_fine_propagate", "fm_fine_propagate_noalloc",
+              "fm_coarse_propagate"):
         getattr(lib, f).restype = ctypes.c_int32
     I64, F32, F64, I32 = ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.c_int32
     lib.fm_mlp_param_count.restype = I32
@@ -205,6 +207,14 @@ def fm_cos(A, C_out, params, dtype="f64", options=None, stream=None):
 def fm_fine_propagate(flow, t_next, t_cur, steps, X_in, X_out, stream=None):
     return _check(lib.fm_fine_propagate(flow, float(t_next), float(t_cur), int(steps), _ptrs(X_in), _ptrs(X_out),
                                         _stream(stream)))
+
+
+def fm_fine_propagate_noalloc(flow, t_next, t_cur, steps, X_in, X_out, stream=None):
+    return _check(lib.fm_fine_propagate_noalloc(flow, float(t_next), float(t_cur), int(steps), _ptrs(X_in),
+                                                _ptrs(X_out), _stream(stream)))
+
+
+FM_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def fm_coarse_propagate(flow, t_next, t_cur, steps, coarse, X_in, X_out, stream=None):
