@@ -71,15 +71,22 @@ typedef enum {
  * inside one fine propagation for the 16-bit types (narrowed from and widened
  * back to the FP64 slice state around it).  FM_BF16X3 splits each
  * operand into BF16 hi + lo parts and forms A_hi B_hi + A_hi B_lo + A_lo B_hi
- * (three BF16 MFMA products, ~16 significant bits). */
+ * (three BF16 MFMA products, ~16 significant bits).  With FM_BF16/FM_F16 the
+ * fixed operand B of the two quadratic flows (A - I for the homotopy, A for
+ * X - X A X) is held as hi + lo planes by default (option split_b): the first
+ * product of each stage field is B_lo Y, then B_hi Y added to it (three
+ * 16-bit products per stage instead of two).  The rounding of B is what the
+ * condition of A(t) amplifies; that of Y and of the products is damped. */
 typedef enum { FM_F64 = 0, FM_F32 = 1, FM_BF16 = 2, FM_F16 = 3, FM_BF16X3 = 4 } fm_dtype;
 
 /* Coarse propagator G. */
 typedef enum {
   FM_COARSE_EULER = 0,    /* forward Euler steps */
-  FM_COARSE_LEARNED = 1   /* degree-3 polynomial step X p(K) + q(K), K = h B X,
+  FM_COARSE_LEARNED = 1,  /* degree-3 polynomial step X p(K) + q(K), K = h B X,
                              coefficients from the loaded network, with a
                              per-slice fallback to Euler (see fm_params)    */
+  FM_COARSE_CN = 2        /* Crank-Nicolson steps (linear flows only; see
+                             FM_FINE_CN)                                    */
 } fm_coarse;
 
 /* Parareal variant.  FM_PARAREAL_MODIFIED is Alg. 3 (linear homogeneous,
@@ -99,8 +106,19 @@ typedef enum { FM_PARAREAL_CLASSICAL = 0, FM_PARAREAL_MODIFIED = 1 } fm_variant;
 /* Fine propagator F. */
 typedef enum {
   FM_FINE_RK4 = 0,    /* classical four-stage Runge-Kutta steps */
-  FM_FINE_EULER = 1   /* forward Euler steps (the fine scheme of the paper's
+  FM_FINE_EULER = 1,  /* forward Euler steps (the fine scheme of the paper's
                          Example 1, Sec. 2) */
+  FM_FINE_CN = 2      /* Crank-Nicolson steps, the scheme of both propagators
+                         in the paper's Example 2 (Sec. 2), for the linear
+                         flows dX/dt = s A X + b I (FM_FLOW_EXP: s = 1, b = 0;
+                         FM_FLOW_INV_LINEAR: s = -1, b = 1):
+                           (I - s h/2 A) X+ = (I + s h/2 A) X + h b I.
+                         Per step size h the library forms
+                         Y = (I - s h/2 A)^{-1} once by an FP64 Newton-Schulz
+                         iteration from Y = I (requires (h/2) ||A||_inf < 0.75,
+                         else FM_ERR_UNSUPPORTED) and D = s Y A, and takes
+                         each step as X+ = X + h (D X + b Y): one product per
+                         step, FP64 state */
 } fm_fine;
 
 typedef struct {
@@ -178,6 +196,8 @@ typedef struct {
  * multiple instead of the tuned one), coarse_f64=0|1 (default 0: coarse-step
  * products, Euler or learned, in FP64 for an FP32 or 16-bit flow, so that the
  * coarse step's own rounding does not floor the parareal increment),
+ * split_b=0|1 (default 1 for FM_BF16 and FM_F16: the fixed operand of the
+ * quadratic flows as hi + lo planes, see fm_dtype; 0: one plane),
  * autotune_cache=<path>,
  * timing=0|1 (default 0: fill the timing fields of fm_stats), verbose=0|1
  * (one stderr line per parareal iteration and per tile choice),

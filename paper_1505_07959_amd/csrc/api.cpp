@@ -98,8 +98,8 @@ fm_status fm_parareal_solve(fm_flow f, const double* const* X0, double* const* X
     const fm_params& p = prm[i];
     if (!(p.T > 0) || !std::isfinite(p.T) || p.N < 1 || p.N > 4096 || p.coarse_steps < 1 || p.fine_steps < 1 ||
         p.max_iter < 0 || p.max_refine < 0 || !(p.tol >= 0) || !(p.refine_tol >= 0) ||
-        (p.coarse != FM_COARSE_EULER && p.coarse != FM_COARSE_LEARNED) ||
-        (p.fine_method != FM_FINE_RK4 && p.fine_method != FM_FINE_EULER) ||
+        (p.coarse != FM_COARSE_EULER && p.coarse != FM_COARSE_LEARNED && p.coarse != FM_COARSE_CN) ||
+        (p.fine_method != FM_FINE_RK4 && p.fine_method != FM_FINE_EULER && p.fine_method != FM_FINE_CN) ||
         (p.variant != FM_PARAREAL_CLASSICAL && p.variant != FM_PARAREAL_MODIFIED)) {
       set_error("prm[%d]: need T > 0, 1 <= N <= 4096, steps >= 1, max_iter >= 0, tol >= 0, known coarse and "
                 "fine schemes and a known variant", i);
@@ -122,6 +122,12 @@ fm_status fm_parareal_solve(fm_flow f, const double* const* X0, double* const* X
     }
     if (f->impl.inst[i].kind == FM_FLOW_INV_HOMOTOPY && p.T != 1.0) {
       set_error("prm[%d]: the homotopy flow reaches A^{-1} at T = 1 only", i);
+      return FM_ERR_INVALID;
+    }
+    if ((p.coarse == FM_COARSE_CN || p.fine_method == FM_FINE_CN) && f->impl.inst[i].kind != FM_FLOW_EXP &&
+        f->impl.inst[i].kind != FM_FLOW_INV_LINEAR) {
+      set_error("prm[%d]: Crank-Nicolson steps are defined for the linear flows (FM_FLOW_EXP, FM_FLOW_INV_LINEAR)",
+                i);
       return FM_ERR_INVALID;
     }
     if (p.coarse == FM_COARSE_LEARNED && f->impl.inst[i].kind != FM_FLOW_INV_HOMOTOPY &&
@@ -173,10 +179,16 @@ fm_status fm_coarse_propagate(fm_flow f, double t_next, double t_cur, int32_t st
   fm::clear_error();
   fm_status s = check_prop(f, t_next, t_cur, steps, X_in, X_out);
   if (s != FM_OK) return s;
-  if (coarse != FM_COARSE_EULER && coarse != FM_COARSE_LEARNED) {
+  if (coarse != FM_COARSE_EULER && coarse != FM_COARSE_LEARNED && coarse != FM_COARSE_CN) {
     set_error("unknown coarse kind %d", coarse);
     return FM_ERR_INVALID;
   }
+  if (coarse == FM_COARSE_CN)
+    for (int i = 0; i < f->impl.batch; ++i)
+      if (f->impl.inst[i].kind != FM_FLOW_EXP && f->impl.inst[i].kind != FM_FLOW_INV_LINEAR) {
+        set_error("problem %d: Crank-Nicolson steps are defined for the linear flows only", i);
+        return FM_ERR_INVALID;
+      }
   return f->impl.coarse_propagate(t_next, t_cur, steps, coarse, X_in, X_out, (hipStream_t)hip_stream);
 }
 

@@ -152,6 +152,11 @@ Flow::~Flow() {
   if (model.d_theta) (void)hipFree(model.d_theta);
   if (model.d_norm) (void)hipFree(model.d_norm);
   for (auto& in : inst) {
+    for (auto& c : in.cn) {
+      if (c.Dop && c.Dop != (void*)c.D64) (void)hipFree(c.Dop);
+      if (c.D64) (void)hipFree(c.D64);
+      if (c.E) (void)hipFree(c.E);
+    }
     if (in.A64) (void)hipFree(in.A64);
     if (in.Bop) (void)hipFree(in.Bop);
     if (in.B64) (void)hipFree(in.B64);
@@ -211,6 +216,9 @@ fm_status Flow::ensure_hredu(size_t count) {
   hredu_cap = count;
   return FM_OK;
 }
+
+// Flows whose stage field takes two products (first P = B Y, then Y P).
+static bool two_products(int kind) { return kind == FM_FLOW_INV_HOMOTOPY || kind == FM_FLOW_INV_STEADY; }
 
 // ------------------------------------------------------------------ configs
 
@@ -475,6 +483,8 @@ fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char*
   if (kv.count("graph")) use_graph = kv["graph"] != "0";
   if (use_graph) FM_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
   if (kv.count("coarse_f64")) coarse64 = kv["coarse_f64"] != "0" && dt != DT_F64;
+  if (kv.count("split_b")) split_b = kv["split_b"] != "0";
+  if (dt != DT_BF16 && dt != DT_F16) split_b = false;
   if (kv.count("pad")) {
     force_pad = atoi(kv["pad"].c_str());
     if (force_pad != 64 && force_pad != 128 && force_pad != 256) {
@@ -505,8 +515,16 @@ fm_status Flow::init(const fm_problem* p, int32_t nb, int32_t dtype, const char*
     FM_HIP(hipMalloc((void**)&in.A64, np2 * sizeof(double)));
     FM_HIP(stage_pad_f64(in.A64, in.np, p[i].A, p[i].n, p[i].lda, st));
     if (in.kind != FM_FLOW_SQRT_STEADY) {
-      FM_HIP(hipMalloc(&in.Bop, np2 * dt_size(dt)));
-      FM_HIP(convert_f64(in.Bop, dt, in.A64, in.kind == FM_FLOW_INV_HOMOTOPY ? -1.0 : 0.0, in.n, in.np, st));
+      const double shift = in.kind == FM_FLOW_INV_HOMOTOPY ? -1.0 : 0.0;
+      if (split_b && two_products(in.kind)) {
+        // hi plane (the operand) followed by the lo plane op(B - hi)
+        FM_HIP(hipMalloc(&in.Bop, 2 * np2 * dt_size(dt)));
+        FM_HIP(convert_split_f64(in.Bop, dt, in.A64, shift, in.n, in.np, st));
+        in.Blo = (char*)in.Bop + np2 * dt_size(dt);
+      } else {
+        FM_HIP(hipMalloc(&in.Bop, np2 * dt_size(dt)));
+        FM_HIP(convert_f64(in.Bop, dt, in.A64, shift, in.n, in.np, st));
+      }
       if (coarse64) FM_TRY(ensure_b64(i, st));
     }
   }
@@ -573,8 +591,6 @@ fm_status Flow::gemm_groups(int epi, std::vector<GItem>& items, const std::vecto
   return FM_OK;
 }
 
-// Flows whose stage field takes two products (first P = B Y, then Y P).
-static bool two_products(int kind) { return kind == FM_FLOW_INV_HOMOTOPY || kind == FM_FLOW_INV_STEADY; }
 
 // The stage-field product of item g (reading stage operand y, and P = B y
 // for the two-product flows): k = s0 (a b) + s1 E + s3 I per flow kind.
@@ -627,6 +643,152 @@ static GItem blank_item(const Inst& in, int i) {
   return it;
 }
 
+// First product of a two-product stage field, out = s0 B Y, onto the item
+// lists `hi` (and `lo`).  With the lo plane of B (16-bit products, option
+// split_b) it is two products: out = s0 B_lo Y (list lo, launched first),
+// then out = s0 B_hi Y + out (list hi): B carries 2 x 8 (or 2 x 11)
+// significant bits, and the small B_lo part is rounded to the operand type
+// before it joins the FP32 accumulation of the main part.
+static void first_product(std::vector<GItem>& hi, std::vector<int>& ihi, std::vector<GItem>& lo,
+                          std::vector<int>& ilo, const Inst& in, int i, const void* b_hi, const void* b_lo,
+                          const void* y, void* out, double s0) {
+  GItem g = blank_item(in, i);
+  g.a = b_hi;
+  g.b = y;
+  g.out0 = out;
+  g.flags = F_E_NONE;
+  g.s[0] = s0;
+  if (b_lo) {
+    GItem q = g;
+    q.a = b_lo;
+    lo.push_back(q);
+    ilo.push_back(i);
+    g.in0 = out;
+    g.s[1] = 1.0;
+    g.flags = 0;
+  }
+  hi.push_back(g);
+  ihi.push_back(i);
+}
+
+// ------------------------------------------------- Crank-Nicolson operators
+// For dX/dt = s A X + b I the Crank-Nicolson step (Sec. 2, Example 2) is
+// X+ = Y ((I + s h/2 A) X + h b I), Y = (I - s h/2 A)^{-1}, which equals
+// X + h (D X + b Y) with D = s Y A.  Y comes from the FP64 Newton-Schulz
+// iteration Y <- Y (2I - M Y), M = I - s h/2 A, from Y = I: its residual
+// I - M Y is squared by every step and starts at s h/2 A, so with
+// rho = (h/2) ||A||_inf < 0.75 the iteration count k with rho^(2^k) < 1e-17
+// reaches FP64 rounding.  Built once per (problem, h); kept with the flow.
+fm_status Flow::ensure_cn(int i, double h, hipStream_t st, const Inst::CnOp** out) {
+  Inst& in = inst[i];
+  for (const auto& c : in.cn)
+    if (c.h == h) {
+      *out = &c;
+      return FM_OK;
+    }
+  if (in.kind != FM_FLOW_EXP && in.kind != FM_FLOW_INV_LINEAR) {
+    set_error("Crank-Nicolson steps are defined for the linear flows only");
+    return FM_ERR_INVALID;
+  }
+  const double s = in.kind == FM_FLOW_EXP ? 1.0 : -1.0;
+  const bool affine = in.kind == FM_FLOW_INV_LINEAR;
+  const size_t np2 = (size_t)in.np * in.np;
+  FM_HIP(hipStreamSynchronize(st));
+  release_graphs();
+  ring.reset();
+  FM_TRY(ensure_hredu(1));
+  double* tmp = nullptr;  // M, Y0, Y1, T and one scalar
+  FM_HIP(hipMalloc((void**)&tmp, (4 * np2 + 1) * sizeof(double)));
+  double *M = tmp, *Y[2] = {tmp + np2, tmp + 2 * np2}, *T = tmp + 3 * np2, *dn = tmp + 4 * np2;
+  auto fail = [&](fm_status r) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(tmp);
+    return r;
+  };
+  if (in.norm_inf < 0) {
+    if (launch_norm_inf(in.A64, in.n, in.np, dn, st) != hipSuccess ||
+        hipMemcpyAsync(hredu, dn, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(hip_status(hipGetLastError(), "Crank-Nicolson: ||A||_inf"));
+    in.norm_inf = hredu[0];
+  }
+  const double rho = 0.5 * std::fabs(h) * in.norm_inf;
+  if (!(rho < 0.75)) {
+    set_error("Crank-Nicolson step h = %g: (h/2) ||A||_inf = %g, the Newton-Schulz inverse needs < 0.75", h, rho);
+    return fail(FM_ERR_UNSUPPORTED);
+  }
+  int k = 0;
+  for (double r = rho; r > 1e-17 && k < 64; r *= r) ++k;
+  Inst::CnOp op{h, nullptr, nullptr, nullptr};
+  auto product = [&](const void* a, const void* b, void* o, double s0, double s2) -> fm_status {
+    std::vector<GItem> items(1);
+    std::vector<int> ii(1, i);
+    GItem& g = items[0];
+    g = blank_item(in, i);
+    g.a = a;
+    g.b = b;
+    g.out0 = o;
+    g.s[0] = s0;
+    g.s[2] = s2;
+    g.flags = F_E_NONE | F_OUT0_F64;
+    return gemm_groups(EPI_AFFINE, items, ii, true, st);
+  };
+  fm_status r = FM_OK;
+  if (set_identity(Y[0], in.n, in.np, st) != hipSuccess) return fail(hip_status(hipGetLastError(), "set_identity"));
+  {
+    LinItem li{nullptr, nullptr, nullptr, Y[0], in.A64, M, nullptr, -0.5 * s * h, (int64_t)np2, 0, LIN_AXPY};
+    if (launch_lincomb(li, st) != hipSuccess) return fail(hip_status(hipGetLastError(), "M = I - s h/2 A"));
+  }
+  int cur = 0;
+  for (int j = 0; j < k && r == FM_OK; ++j) {
+    r = product(M, Y[cur], T, -1.0, 2.0);               // T = 2I - M Y
+    if (r == FM_OK) r = product(Y[cur], T, Y[cur ^ 1], 1.0, 0.0);  // Y <- Y T
+    cur ^= 1;
+  }
+  if (r != FM_OK) return fail(r);
+  if (hipMalloc((void**)&op.D64, np2 * 8) != hipSuccess) return fail(hip_status(hipErrorOutOfMemory, "hipMalloc(D)"));
+  r = product(Y[cur], in.A64, op.D64, s, 0.0);          // D = s Y A
+  if (r == FM_OK && affine) {
+    if (hipMalloc((void**)&op.E, np2 * 8) != hipSuccess || copy_f64(op.E, Y[cur], (int64_t)np2, st) != hipSuccess)
+      r = hip_status(hipErrorOutOfMemory, "Crank-Nicolson: E");
+  }
+  if (r == FM_OK) {
+    if (dt == DT_F64) {
+      op.Dop = op.D64;
+    } else if (hipMalloc(&op.Dop, np2 * dt_size(dt)) != hipSuccess ||
+               convert_f64(op.Dop, dt, op.D64, 0.0, in.n, in.np, st) != hipSuccess) {
+      r = hip_status(hipErrorOutOfMemory, "Crank-Nicolson: D in the product dtype");
+    }
+  }
+  if (r != FM_OK) {
+    (void)hipStreamSynchronize(st);
+    if (op.Dop && op.Dop != (void*)op.D64) (void)hipFree(op.Dop);
+    if (op.D64) (void)hipFree(op.D64);
+    if (op.E) (void)hipFree(op.E);
+    return fail(r);
+  }
+  FM_HIP(hipStreamSynchronize(st));
+  (void)hipFree(tmp);
+  ring.reset();
+  in.cn.push_back(op);
+  *out = &in.cn.back();
+  return FM_OK;
+}
+
+// The Crank-Nicolson step as an Euler-form item: k = D Y + b E, X+ = X + h k.
+static void cn_item(GItem& g, const Inst::CnOp& op, const void* dop, void* y) {
+  g.a = dop;
+  g.b = y;
+  g.s[0] = 1.0;
+  if (op.E) {
+    g.in0 = op.E;
+    g.s[1] = 1.0;
+    g.flags = F_E_F64;
+  } else {
+    g.flags = F_E_NONE;
+  }
+}
+
 // ------------------------------------------------------- fine propagator
 // `steps` classical RK4 steps of size slot.h on every slot, in place on
 // slot.x; slot.ya must hold op(x) on entry.  One grouped launch per product:
@@ -640,8 +802,13 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
   // RK4: one unit = one step of 4 stages (operands ya -> yb -> ya -> yb -> ya).
   // Forward Euler: one unit = two steps (ya -> yb -> ya); an odd step count
   // ends with one more step on the first list (result operand in yb).
-  const bool euler = method == FM_FINE_EULER;
+  const bool cn = method == FM_FINE_CN;
+  const bool euler = method == FM_FINE_EULER || cn;  // one product per step, FP64 state
   const int nst = euler ? 2 : 4;
+  // Crank-Nicolson operators of every slot (built before any list is staged)
+  std::vector<const Inst::CnOp*> cnop(slots.size(), nullptr);
+  if (cn)
+    for (size_t k = 0; k < slots.size(); ++k) FM_TRY(ensure_cn(slots[k].inst, slots[k].h, st, &cnop[k]));
   const int units = euler ? steps / 2 : steps;
   const bool tail = euler && (steps % 2 == 1);
   const int fepi = euler ? EPI_EULER : EPI_RK4;
@@ -666,26 +833,19 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
       widen.push_back(CastItem{xs[k], slots[k].x, np2, 0, 0});
     }
   }
-  std::vector<GItem> l1[4], l2[4];
-  std::vector<int> i1[4], i2[4];
+  std::vector<GItem> l0[4], l1[4], l2[4];
+  std::vector<int> i0[4], i1[4], i2[4];
   for (int s = 0; s < nst; ++s) {
     for (size_t k = 0; k < slots.size(); ++k) {
       const FineSlot& sl = slots[k];
       const Inst& in = inst[sl.inst];
       void* ycur = (s % 2 == 0) ? sl.ya : sl.yb;
       void* ynext = (s % 2 == 0) ? sl.yb : sl.ya;
-      if (two_products(in.kind)) {
-        GItem g = blank_item(in, sl.inst);
-        g.a = in.Bop;
-        g.b = ycur;
-        g.out0 = sl.p;
-        g.flags = F_E_NONE;
-        g.s[0] = 1.0;
-        l1[s].push_back(g);
-        i1[s].push_back(sl.inst);
-      }
+      if (two_products(in.kind))
+        first_product(l1[s], i1[s], l0[s], i0[s], in, sl.inst, in.Bop, in.Blo, ycur, sl.p, 1.0);
       GItem g = blank_item(in, sl.inst);
-      field_item(g, in, ycur, sl.p);
+      if (cn) cn_item(g, *cnop[k], cnop[k]->Dop, ycur);
+      else field_item(g, in, ycur, sl.p);
       g.out0 = ynext;
       g.out1 = euler ? (void*)sl.x : sl.kacc;
       g.x = x32 ? (double*)(void*)xs[k] : sl.x;
@@ -712,7 +872,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
     // every list below is launched `steps` times: no ring reset in between
     size_t need = 0;
     for (int s = 0; s < nst; ++s)
-      need += (l1[s].size() + l2[s].size()) * (sizeof(GItem) + sizeof(int)) + 8 * 512;
+      need += (l0[s].size() + l1[s].size() + l2[s].size()) * (sizeof(GItem) + sizeof(int)) + 12 * 512;
     need += 2 * (slots.size() * sizeof(CastItem) + 512);
     FM_TRY(reserve_ring(need, st));
   }
@@ -768,6 +928,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
   };
   size_t first_stage_end = 0;  // launches of the first list (the Euler tail)
   for (int s = 0; s < nst; ++s) {
+    FM_TRY(prepare(l0[s], i0[s], EPI_AFFINE));
     FM_TRY(prepare(l1[s], i1[s], EPI_AFFINE));
     FM_TRY(prepare(l2[s], i2[s], fepi));
     if (s == 0) first_stage_end = seq.size();
@@ -866,6 +1027,9 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
   // option coarse_f64: operands, products and B in FP64 (B64 is made at
   // flow creation)
   auto cbop = [&](const Inst& in) -> void* { return coarse64 ? (void*)in.B64 : in.Bop; };
+  std::vector<const Inst::CnOp*> cnop(slots.size(), nullptr);
+  for (size_t k = 0; k < slots.size(); ++k)
+    if (slots[k].cn) FM_TRY(ensure_cn(slots[k].inst, slots[k].h, st, &cnop[k]));
   {
     std::vector<PrepItem> prep;
     for (const CoarseSlot& sl : slots) {
@@ -883,27 +1047,23 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
     FM_TRY(push(prep.data(), prep.size() * sizeof(PrepItem), &d, st));
     FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), coarse64 ? DT_F64 : dt, nullptr, st));
   }
+  // lo plane of B for the first product (none with FP64 coarse products)
+  auto cblo = [&](const Inst& in) -> const void* { return coarse64 ? nullptr : in.Blo; };
   for (int j = 0; j < steps; ++j) {
-    std::vector<GItem> l1, l2, l3, l4;
-    std::vector<int> i1, i2, i3, i4;
-    for (const CoarseSlot& sl : slots) {
+    std::vector<GItem> l0, l1, l2, l3, l4;
+    std::vector<int> i0, i1, i2, i3, i4;
+    for (size_t sk = 0; sk < slots.size(); ++sk) {
+      const CoarseSlot& sl = slots[sk];
       const Inst& in = inst[sl.inst];
       void* yin = (j % 2 == 0) ? sl.y0 : sl.y1;
       void* yout = (j % 2 == 0) ? sl.y1 : sl.y0;
       const double* x = (j == 0) ? sl.xin : sl.xout;
       if (!sl.learned) {
-        if (two_products(in.kind)) {
-          GItem g = blank_item(in, sl.inst);
-          g.a = cbop(in);
-          g.b = yin;
-          g.out0 = sl.p;
-          g.flags = F_E_NONE;
-          g.s[0] = 1.0;
-          l1.push_back(g);
-          i1.push_back(sl.inst);
-        }
+        if (two_products(in.kind))
+          first_product(l1, i1, l0, i0, in, sl.inst, cbop(in), cblo(in), yin, sl.p, 1.0);
         GItem g = blank_item(in, sl.inst);
-        field_item(g, in, yin, sl.p, cbop(in));
+        if (sl.cn) cn_item(g, *cnop[sk], coarse64 ? (void*)cnop[sk]->D64 : cnop[sk]->Dop, yin);
+        else field_item(g, in, yin, sl.p, cbop(in));
         g.out0 = yout;
         g.out1 = sl.xout;
         g.x = const_cast<double*>(x);
@@ -914,14 +1074,7 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
         // K = h B Y ; K2 = K K ; P = c0 I + c1 K + c2 K2 + c3 K2 K (and K3) ;
         // X+ = Y P + c4 I + c5 K + c6 K2 + c7 K3
         const double* c = sl.coef + 8 * j;
-        GItem g = blank_item(in, sl.inst);
-        g.a = cbop(in);
-        g.b = yin;
-        g.out0 = sl.k1;
-        g.flags = F_E_NONE;
-        g.s[0] = sl.h;
-        l1.push_back(g);
-        i1.push_back(sl.inst);
+        first_product(l1, i1, l0, i0, in, sl.inst, cbop(in), cblo(in), yin, sl.k1, sl.h);
         GItem g2 = blank_item(in, sl.inst);
         g2.a = sl.k1;
         g2.b = sl.k1;
@@ -962,9 +1115,11 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
       return FM_ERR_INVALID;
     }
     if (!any_learned) {
+      FM_TRY(gemm_groups(EPI_AFFINE, l0, i0, coarse64, st));
       FM_TRY(gemm_groups(EPI_AFFINE, l1, i1, coarse64, st));
       FM_TRY(gemm_groups(EPI_EULER, l2, i2, coarse64, st));
     } else {
+      FM_TRY(gemm_groups(EPI_AFFINE, l0, i0, coarse64, st));
       FM_TRY(gemm_groups(EPI_AFFINE, l1, i1, coarse64, st));
       FM_TRY(gemm_groups(EPI_AFFINE, l2, i2, coarse64, st));
       FM_TRY(gemm_groups(EPI_POLYP, l3, i3, coarse64, st));
@@ -1084,6 +1239,7 @@ fm_status Flow::coarse_propagate(double t1, double t0, int steps, int coarse, co
       s.t0 = t0;
       s.h = (t1 - t0) / steps;
       s.learned = coarse == FM_COARSE_LEARNED;
+      s.cn = coarse == FM_COARSE_CN;
       s.coef = coefs.data() + (size_t)i * 8 * steps;
     }
     if (pass == 0) FM_TRY(prop.reserve(prop.used));
@@ -1251,6 +1407,7 @@ fm_status Flow::solve(const double* const* X0, double* const* Xout, const fm_par
     c.h = (tb - ta) / C;
     c.learned = learned ? 1 : 0;
     c.coef = learned ? &w[i].coef[(size_t)s * C * 8] : nullptr;
+    c.cn = prm[i].coarse == FM_COARSE_CN ? 1 : 0;
     return c;
   };
   // coarse steps of one sweep position, split by coarse kind and step count

@@ -78,9 +78,21 @@ struct Inst {
   GemmCfg cfg{};     // product config in the flow dtype
   GemmCfg cfg64{};   // FP64 config (residual / refinement)
   double* A64 = nullptr;  // padded FP64 A
-  void* Bop = nullptr;    // right operand of the first product: A - I (homotopy) or A
+  void* Bop = nullptr;    // left operand of the first product: A - I (homotopy) or A
+  void* Blo = nullptr;    // its lo plane op(B - Bop) (16-bit products, option split_b), inside Bop's allocation
   double* B64 = nullptr;  // the same in FP64 (learned-step features; made on first use)
   double mu[4] = {0, 0, 0, 0};  // tr((A - I)^j) / n
+  // Crank-Nicolson operators per step size (linear flows): D = s Y A,
+  // Y = (I - s h/2 A)^{-1}; E = b Y (null when b = 0); Dop = D in the
+  // product dtype (== D64 for FP64)
+  struct CnOp {
+    double h;
+    double* D64;
+    void* Dop;
+    double* E;
+  };
+  std::vector<CnOp> cn;
+  double norm_inf = -1.0;  // ||A||_inf (made on first use)
 };
 
 // Per-slot buffers of one propagation.
@@ -106,8 +118,9 @@ struct CoarseSlot {
   void* k3;
   double t0;          // time at the slot start (learned-step network input)
   double h;           // substep size
-  int learned;        // 1: learned polynomial step, 0: Euler
+  int learned;        // 1: learned polynomial step, 0: Euler (or Crank-Nicolson)
   const double* coef; // host: 8 coefficients per substep (learned)
+  int cn = 0;         // 1: Crank-Nicolson substeps (linear flows)
 };
 
 struct Flow {
@@ -120,6 +133,7 @@ struct Flow {
   int force_bm = 0, force_bk = 0;  // option tile=<bm>x<bk>: fixed product tile (flow dtype)
   int force_pad = 0;                // option pad=64|128|256: fixed padding multiple
   bool coarse64 = false;            // option coarse_f64=1: coarse-step products in FP64
+  bool split_b = true;              // option split_b=0|1: 16-bit fixed operand as hi + lo planes
   // bytes per element of the coarse step's operand scratch
   size_t coarse_esz() const { return coarse64 ? 8 : dt_size(dt); }
   fm_status ensure_b64(int i, hipStream_t st);
@@ -194,6 +208,8 @@ struct Flow {
 
   // ws == nullptr: workspace from the flow's propagator arena (grown on
   // demand); else the caller's ws_cap bytes at ws, and nothing is allocated
+  // Crank-Nicolson operators of problem i for step size h (built once)
+  fm_status ensure_cn(int i, double h, hipStream_t st, const Inst::CnOp** out);
   fm_status fine_propagate(double t1, double t0, int steps, const double* const* xin, double* const* xout,
                            hipStream_t st, char* ws = nullptr, size_t ws_cap = 0);
   fm_status coarse_propagate(double t1, double t0, int steps, int coarse, const double* const* xin,

@@ -398,6 +398,20 @@ hipError_t convert_f64(void* dst, int dt, const double* src, double shift, int n
   return hipGetLastError();
 }
 
+hipError_t convert_split_f64(void* dst, int dt, const double* src, double shift, int n, int np, hipStream_t st) {
+  dim3 g(ew_grid((int64_t)np * np)), b(EW_THREADS);
+  switch (dt) {
+    case DT_BF16:
+      hipLaunchKernelGGL((k_convert<__bf16, true>), g, b, 0, st, (__bf16*)dst, src, shift, n, np);
+      break;
+    case DT_F16:
+      hipLaunchKernelGGL((k_convert<_Float16, true>), g, b, 0, st, (_Float16*)dst, src, shift, n, np);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t fill_pattern(void* dst, int dt, int64_t count, hipStream_t st) {
   dim3 g(ew_grid(count)), b(EW_THREADS);
   switch (dt) {

@@ -90,6 +90,9 @@ int gemm_max_grid(const GemmCfg& cfg);
 hipError_t stage_pad_f64(double* dst, int np, const double* src, int64_t n, int64_t ld, hipStream_t st);
 // dst(op dtype, np x np) <- src(FP64) + shift*I (shift only on the leading n x n diagonal)
 hipError_t convert_f64(void* dst, int dt, const double* src, double shift, int n, int np, hipStream_t st);
+// The same as two planes of a 16-bit type (DT_BF16 or DT_F16): hi = op(v) at
+// dst, lo = op(v - hi) at dst + np*np elements.
+hipError_t convert_split_f64(void* dst, int dt, const double* src, double shift, int n, int np, hipStream_t st);
 // dst (count elements of dtype dt) <- a fixed non-trivial pattern (for timing)
 hipError_t fill_pattern(void* dst, int dt, int64_t count, hipStream_t st);
 // dst(FP64 np x np) <- identity on the leading n x n block

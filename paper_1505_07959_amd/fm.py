@@ -27,8 +27,8 @@ FM_FLOW_EXP = 4
 FM_FLOW_INV_LINEAR = 5
 
 FM_F64, FM_F32, FM_BF16, FM_F16, FM_BF16X3 = 0, 1, 2, 3, 4
-FM_COARSE_EULER, FM_COARSE_LEARNED = 0, 1
-FM_FINE_RK4, FM_FINE_EULER = 0, 1
+FM_COARSE_EULER, FM_COARSE_LEARNED, FM_COARSE_CN = 0, 1, 2
+FM_FINE_RK4, FM_FINE_EULER, FM_FINE_CN = 0, 1, 2
 FM_PARAREAL_CLASSICAL, FM_PARAREAL_MODIFIED = 0, 1
 
 DTYPES = {"f64": FM_F64, "f32": FM_F32, "bf16": FM_BF16, "f16": FM_F16, "bf16x3": FM_BF16X3}

@@ -36,9 +36,9 @@ def _exact(kind, Q, lam):
     return (Q * f) @ Q.T
 
 
-def _run(cases, dtype, refine):
+def _run(cases, dtype, refine, options=None):
     from paper_1505_07959_amd import fm
-    h = fm.fm_flow_create([(k, dev(A)) for k, T, A, Q, lam in cases], dtype)
+    h = fm.fm_flow_create([(k, dev(A)) for k, T, A, Q, lam in cases], dtype, options)
     try:
         outs = [empty(A.shape[0]) for _, _, A, _, _ in cases]
         st, stats = fm.fm_parareal_solve(h, None, outs, [_params(k, T, refine) for k, T, *_ in cases])
@@ -47,11 +47,17 @@ def _run(cases, dtype, refine):
         fm.fm_destroy(h)
 
 
-def test_batched_bf16_before_and_after_refinement():
+@pytest.mark.parametrize("options", [None, "split_b=0"])
+def test_batched_bf16_before_and_after_refinement(options):
+    """BF16 products, by default with the fixed operand (A - I, A) as hi + lo
+    BF16 planes: both halves within the 1e-2 pre-refinement bar.  With
+    split_b=0 (plain BF16 operands) the inverse half misses it (the 2^-9
+    rounding of A - I amplified by the condition of A(t), up to 1e3), the
+    square-root half does not; refinement reaches 1e-10 either way."""
     cases = [inputs.batched_instance(i, max_n=256) for i in range(12)]
-    say("sizes %s" % [c[2].shape[0] for c in cases])
-    st0, stats0, X0 = _run(cases, "bf16", refine=False)
-    st1, stats1, X1 = _run(cases, "bf16", refine=True)
+    say("sizes %s, options %s" % ([c[2].shape[0] for c in cases], options))
+    st0, stats0, X0 = _run(cases, "bf16", refine=False, options=options)
+    st1, stats1, X1 = _run(cases, "bf16", refine=True, options=options)
     worst_pre = {HOMOTOPY: 0.0, SQRT: 0.0}
     for (kind, T, A, Q, lam), s0, x0, s1, x1 in zip(cases, stats0, X0, stats1, X1):
         ref = _oracle(kind, T, Q, lam, s0["iters"])
@@ -66,6 +72,8 @@ def test_batched_bf16_before_and_after_refinement():
         assert e_post <= 1e-10
     say("worst pre-refinement error: inverse %.2e, square root %.2e" % (worst_pre[HOMOTOPY], worst_pre[SQRT]))
     assert worst_pre[SQRT] <= 1e-2
+    if options is None:
+        assert worst_pre[HOMOTOPY] <= 1e-2
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
