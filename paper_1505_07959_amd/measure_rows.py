@@ -56,6 +56,17 @@ def example1():
             "note": "latency-bound: 5000 Euler steps of 80 x 80 products per fine sweep"}
 
 
+def example2_cn():
+    """Sec. 2, Example 2 at the paper's sizes: exp(B), B = -A / 2^10 with the
+    Example 1 Laplacian (n = 80), N = 25, J = 200, Crank-Nicolson fine and
+    coarse steps, to increment 1e-10."""
+    B = torch.from_numpy(-inputs.laplacian_1d(80) / 2 ** 10).cuda()
+    s, sec = _solve(fm.FM_FLOW_EXP, B, {"T": 1.0, "N": 25, "fine_steps": 200, "max_iter": 25, "tol": 1e-10,
+                                        "fine_method": fm.FM_FINE_CN, "coarse": fm.FM_COARSE_CN})
+    return {"workload": "example2_laplacian80_crank_nicolson_N25_J200", "iterations": s["iters"], "seconds": sec,
+            "note": "latency-bound: 5000 Crank-Nicolson steps of 80 x 80 products per fine sweep"}
+
+
 def exp_variants(n=2048):
     """exp(T A) by the exponential flow, A = -(SPD, lam in [0.05, 4]), N = 16,
     16 RK4 steps per slice, FP64, to increment 1e-10: classical vs modified."""
@@ -181,7 +192,7 @@ def learned_vs_euler(kind=fm.FM_FLOW_INV_HOMOTOPY, dtype=None, tol=None, options
     return res
 
 
-ROWS = {"example1": example1, "exp": exp_variants, "aima": aima, "cos": cosine, "batched": batched,
+ROWS = {"example1": example1, "example2_cn": example2_cn, "exp": exp_variants, "aima": aima, "cos": cosine, "batched": batched,
         "batched_tol1e-2": lambda: batched(tol=1e-2),
         "learned": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY),
         "learned_f32": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY, "f32", 1e-6),
