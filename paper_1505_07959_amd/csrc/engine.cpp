@@ -706,10 +706,10 @@ fm_status Flow::ensure_cn(int i, double h, hipStream_t st, const Inst::CnOp** ou
     return r;
   };
   if (in.norm_inf < 0) {
-    if (launch_norm_inf(in.A64, in.n, in.np, dn, st) != hipSuccess ||
-        hipMemcpyAsync(hredu, dn, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      return fail(hip_status(hipGetLastError(), "Crank-Nicolson: ||A||_inf"));
+    hipError_t e = launch_norm_inf(in.A64, in.n, in.np, dn, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hredu, dn, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(hip_status(e, "Crank-Nicolson: ||A||_inf"));
     in.norm_inf = hredu[0];
   }
   const double rho = 0.5 * std::fabs(h) * in.norm_inf;
@@ -734,10 +734,11 @@ fm_status Flow::ensure_cn(int i, double h, hipStream_t st, const Inst::CnOp** ou
     return gemm_groups(EPI_AFFINE, items, ii, true, st);
   };
   fm_status r = FM_OK;
-  if (set_identity(Y[0], in.n, in.np, st) != hipSuccess) return fail(hip_status(hipGetLastError(), "set_identity"));
   {
+    hipError_t e = set_identity(Y[0], in.n, in.np, st);
     LinItem li{nullptr, nullptr, nullptr, Y[0], in.A64, M, nullptr, -0.5 * s * h, (int64_t)np2, 0, LIN_AXPY};
-    if (launch_lincomb(li, st) != hipSuccess) return fail(hip_status(hipGetLastError(), "M = I - s h/2 A"));
+    if (e == hipSuccess) e = launch_lincomb(li, st);
+    if (e != hipSuccess) return fail(hip_status(e, "Crank-Nicolson: M = I - s h/2 A"));
   }
   int cur = 0;
   for (int j = 0; j < k && r == FM_OK; ++j) {
@@ -746,18 +747,23 @@ fm_status Flow::ensure_cn(int i, double h, hipStream_t st, const Inst::CnOp** ou
     cur ^= 1;
   }
   if (r != FM_OK) return fail(r);
-  if (hipMalloc((void**)&op.D64, np2 * 8) != hipSuccess) return fail(hip_status(hipErrorOutOfMemory, "hipMalloc(D)"));
+  {
+    hipError_t e = hipMalloc((void**)&op.D64, np2 * 8);
+    if (e != hipSuccess) return fail(hip_status(e, "Crank-Nicolson: hipMalloc(D)"));
+  }
   r = product(Y[cur], in.A64, op.D64, s, 0.0);          // D = s Y A
   if (r == FM_OK && affine) {
-    if (hipMalloc((void**)&op.E, np2 * 8) != hipSuccess || copy_f64(op.E, Y[cur], (int64_t)np2, st) != hipSuccess)
-      r = hip_status(hipErrorOutOfMemory, "Crank-Nicolson: E");
+    hipError_t e = hipMalloc((void**)&op.E, np2 * 8);
+    if (e == hipSuccess) e = copy_f64(op.E, Y[cur], (int64_t)np2, st);
+    if (e != hipSuccess) r = hip_status(e, "Crank-Nicolson: E");
   }
   if (r == FM_OK) {
     if (dt == DT_F64) {
       op.Dop = op.D64;
-    } else if (hipMalloc(&op.Dop, np2 * dt_size(dt)) != hipSuccess ||
-               convert_f64(op.Dop, dt, op.D64, 0.0, in.n, in.np, st) != hipSuccess) {
-      r = hip_status(hipErrorOutOfMemory, "Crank-Nicolson: D in the product dtype");
+    } else {
+      hipError_t e = hipMalloc(&op.Dop, np2 * dt_size(dt));
+      if (e == hipSuccess) e = convert_f64(op.Dop, dt, op.D64, 0.0, in.n, in.np, st);
+      if (e != hipSuccess) r = hip_status(e, "Crank-Nicolson: D in the product dtype");
     }
   }
   if (r != FM_OK) {

@@ -1,6 +1,7 @@
 // Host-side engine of libfm: the flow object, propagators, parareal driver.
 #pragma once
 
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -91,7 +92,7 @@ struct Inst {
     void* Dop;
     double* E;
   };
-  std::vector<CnOp> cn;
+  std::deque<CnOp> cn;  // deque: references stay valid as entries are added
   double norm_inf = -1.0;  // ||A||_inf (made on first use)
 };
 
