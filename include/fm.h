@@ -74,9 +74,10 @@ typedef enum {
  * (three BF16 MFMA products, ~16 significant bits).  With FM_BF16/FM_F16 the
  * fixed operand B of the two quadratic flows (A - I for the homotopy, A for
  * X - X A X) is held as hi + lo planes by default (option split_b): the first
- * product of each stage field is B_lo Y, then B_hi Y added to it (three
- * 16-bit products per stage instead of two).  The rounding of B is what the
- * condition of A(t) amplifies; that of Y and of the products is damped. */
+ * product of each stage field is B_hi Y + B_lo Y, both planes in one launch
+ * with one FP32 accumulation (the MFMA work of three 16-bit products per
+ * stage instead of two).  The rounding of B is what the condition of A(t)
+ * amplifies; that of Y and of the products is damped. */
 typedef enum { FM_F64 = 0, FM_F32 = 1, FM_BF16 = 2, FM_F16 = 3, FM_BF16X3 = 4 } fm_dtype;
 
 /* Coarse propagator G. */

@@ -644,31 +644,20 @@ static GItem blank_item(const Inst& in, int i) {
 }
 
 // First product of a two-product stage field, out = s0 B Y, onto the item
-// lists `hi` (and `lo`).  With the lo plane of B (16-bit products, option
-// split_b) it is two products: out = s0 B_lo Y (list lo, launched first),
-// then out = s0 B_hi Y + out (list hi): B carries 2 x 8 (or 2 x 11)
-// significant bits, and the small B_lo part is rounded to the operand type
-// before it joins the FP32 accumulation of the main part.
-static void first_product(std::vector<GItem>& hi, std::vector<int>& ihi, std::vector<GItem>& lo,
-                          std::vector<int>& ilo, const Inst& in, int i, const void* b_hi, const void* b_lo,
-                          const void* y, void* out, double s0) {
+// list.  With the lo plane of B (16-bit products, option split_b, stored
+// right after the hi plane) the product runs over both planes in one
+// launch, out = s0 (B_hi Y + B_lo Y) with one FP32 accumulation: B carries
+// 2 x 8 (or 2 x 11) significant bits.
+static void first_product(std::vector<GItem>& items, std::vector<int>& ii, const Inst& in, int i,
+                          const void* b, bool split, const void* y, void* out, double s0) {
   GItem g = blank_item(in, i);
-  g.a = b_hi;
+  g.a = b;
   g.b = y;
   g.out0 = out;
-  g.flags = F_E_NONE;
+  g.flags = F_E_NONE | (split ? F_SPLIT_A : 0);
   g.s[0] = s0;
-  if (b_lo) {
-    GItem q = g;
-    q.a = b_lo;
-    lo.push_back(q);
-    ilo.push_back(i);
-    g.in0 = out;
-    g.s[1] = 1.0;
-    g.flags = 0;
-  }
-  hi.push_back(g);
-  ihi.push_back(i);
+  items.push_back(g);
+  ii.push_back(i);
 }
 
 // ------------------------------------------------- Crank-Nicolson operators
@@ -839,16 +828,15 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
       widen.push_back(CastItem{xs[k], slots[k].x, np2, 0, 0});
     }
   }
-  std::vector<GItem> l0[4], l1[4], l2[4];
-  std::vector<int> i0[4], i1[4], i2[4];
+  std::vector<GItem> l1[4], l2[4];
+  std::vector<int> i1[4], i2[4];
   for (int s = 0; s < nst; ++s) {
     for (size_t k = 0; k < slots.size(); ++k) {
       const FineSlot& sl = slots[k];
       const Inst& in = inst[sl.inst];
       void* ycur = (s % 2 == 0) ? sl.ya : sl.yb;
       void* ynext = (s % 2 == 0) ? sl.yb : sl.ya;
-      if (two_products(in.kind))
-        first_product(l1[s], i1[s], l0[s], i0[s], in, sl.inst, in.Bop, in.Blo, ycur, sl.p, 1.0);
+      if (two_products(in.kind)) first_product(l1[s], i1[s], in, sl.inst, in.Bop, in.Blo != nullptr, ycur, sl.p, 1.0);
       GItem g = blank_item(in, sl.inst);
       if (cn) cn_item(g, *cnop[k], cnop[k]->Dop, ycur);
       else field_item(g, in, ycur, sl.p);
@@ -878,7 +866,7 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
     // every list below is launched `steps` times: no ring reset in between
     size_t need = 0;
     for (int s = 0; s < nst; ++s)
-      need += (l0[s].size() + l1[s].size() + l2[s].size()) * (sizeof(GItem) + sizeof(int)) + 12 * 512;
+      need += (l1[s].size() + l2[s].size()) * (sizeof(GItem) + sizeof(int)) + 8 * 512;
     need += 2 * (slots.size() * sizeof(CastItem) + 512);
     FM_TRY(reserve_ring(need, st));
   }
@@ -934,7 +922,6 @@ fm_status Flow::run_fine(const std::vector<FineSlot>& slots, int steps, int meth
   };
   size_t first_stage_end = 0;  // launches of the first list (the Euler tail)
   for (int s = 0; s < nst; ++s) {
-    FM_TRY(prepare(l0[s], i0[s], EPI_AFFINE));
     FM_TRY(prepare(l1[s], i1[s], EPI_AFFINE));
     FM_TRY(prepare(l2[s], i2[s], fepi));
     if (s == 0) first_stage_end = seq.size();
@@ -1053,11 +1040,11 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
     FM_TRY(push(prep.data(), prep.size() * sizeof(PrepItem), &d, st));
     FM_HIP(launch_prep((const PrepItem*)d, (int)prep.size(), coarse64 ? DT_F64 : dt, nullptr, st));
   }
-  // lo plane of B for the first product (none with FP64 coarse products)
-  auto cblo = [&](const Inst& in) -> const void* { return coarse64 ? nullptr : in.Blo; };
+  // B as two planes for the first product (not with FP64 coarse products)
+  auto csplit = [&](const Inst& in) -> bool { return !coarse64 && in.Blo != nullptr; };
   for (int j = 0; j < steps; ++j) {
-    std::vector<GItem> l0, l1, l2, l3, l4;
-    std::vector<int> i0, i1, i2, i3, i4;
+    std::vector<GItem> l1, l2, l3, l4;
+    std::vector<int> i1, i2, i3, i4;
     for (size_t sk = 0; sk < slots.size(); ++sk) {
       const CoarseSlot& sl = slots[sk];
       const Inst& in = inst[sl.inst];
@@ -1065,8 +1052,7 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
       void* yout = (j % 2 == 0) ? sl.y1 : sl.y0;
       const double* x = (j == 0) ? sl.xin : sl.xout;
       if (!sl.learned) {
-        if (two_products(in.kind))
-          first_product(l1, i1, l0, i0, in, sl.inst, cbop(in), cblo(in), yin, sl.p, 1.0);
+        if (two_products(in.kind)) first_product(l1, i1, in, sl.inst, cbop(in), csplit(in), yin, sl.p, 1.0);
         GItem g = blank_item(in, sl.inst);
         if (sl.cn) cn_item(g, *cnop[sk], coarse64 ? (void*)cnop[sk]->D64 : cnop[sk]->Dop, yin);
         else field_item(g, in, yin, sl.p, cbop(in));
@@ -1080,7 +1066,7 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
         // K = h B Y ; K2 = K K ; P = c0 I + c1 K + c2 K2 + c3 K2 K (and K3) ;
         // X+ = Y P + c4 I + c5 K + c6 K2 + c7 K3
         const double* c = sl.coef + 8 * j;
-        first_product(l1, i1, l0, i0, in, sl.inst, cbop(in), cblo(in), yin, sl.k1, sl.h);
+        first_product(l1, i1, in, sl.inst, cbop(in), csplit(in), yin, sl.k1, sl.h);
         GItem g2 = blank_item(in, sl.inst);
         g2.a = sl.k1;
         g2.b = sl.k1;
@@ -1121,11 +1107,9 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
       return FM_ERR_INVALID;
     }
     if (!any_learned) {
-      FM_TRY(gemm_groups(EPI_AFFINE, l0, i0, coarse64, st));
       FM_TRY(gemm_groups(EPI_AFFINE, l1, i1, coarse64, st));
       FM_TRY(gemm_groups(EPI_EULER, l2, i2, coarse64, st));
     } else {
-      FM_TRY(gemm_groups(EPI_AFFINE, l0, i0, coarse64, st));
       FM_TRY(gemm_groups(EPI_AFFINE, l1, i1, coarse64, st));
       FM_TRY(gemm_groups(EPI_AFFINE, l2, i2, coarse64, st));
       FM_TRY(gemm_groups(EPI_POLYP, l3, i3, coarse64, st));

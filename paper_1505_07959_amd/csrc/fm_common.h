@@ -41,6 +41,7 @@ enum : int {
   F_E_F64 = 2,      // in0 is FP64 (else operand type) -- EPI_AFFINE/RK4/EULER
   F_E_NONE = 4,     // no E term
   F_X_F32 = 8,      // the RK4 state x is FP32 (16-bit products only)
+  F_SPLIT_A = 16,   // BF16/FP16: a is two planes (hi, lo at + np^2); product = a_hi b + a_lo b
 };
 
 // One matrix product of a grouped launch.  All matrices are np x np,

@@ -643,6 +643,10 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
 
     const int64_t np2 = (int64_t)np * np;
     const int nkps = np / BK;  // K tiles per segment
+    // F_SPLIT_A (16-bit types): the left operand is two planes, hi then lo at
+    // + np^2, and the product is A_hi B + A_lo B, one K segment each,
+    // accumulated in FP32 in that order
+    const bool split_a = (DT == DT_BF16 || DT == DT_F16) && (it.flags & F_SPLIT_A);
     // Global loads through buffer resources rebased at every K tile: the
     // per-lane byte offsets are loop-invariant and small, and a resource's
     // record count is the exact extent of the tile's panel, so a load can
@@ -651,8 +655,8 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
       // segment 0: (A_hi, B_hi); 1: (A_hi, B_lo); 2: (A_lo, B_hi)
       const int seg = kt / nkps;
       const int k0 = (kt - seg * nkps) * BK;
-      const T* As_g = Ag + (seg == 2 ? np2 : 0) + k0;
-      const T* Bs_g = Bg + (seg == 1 ? np2 : 0) + (int64_t)k0 * np;
+      const T* As_g = Ag + (split_a ? seg * np2 : (seg == 2 ? np2 : 0)) + k0;
+      const T* Bs_g = Bg + (!split_a && seg == 1 ? np2 : 0) + (int64_t)k0 * np;
       const __amdgpu_buffer_rsrc_t ra_rs = __builtin_amdgcn_make_buffer_rsrc(
           const_cast<T*>(As_g), (short)0, ((BM - 1) * np + BK) * (int)sizeof(T), 0x00020000);
       const __amdgpu_buffer_rsrc_t rb_rs = __builtin_amdgcn_make_buffer_rsrc(
@@ -739,7 +743,7 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
     // barrier publishes it, its first fragments are requested and only then
     // are the last MFMAs of the current tile issued, so they cover the LDS
     // latency; the global loads of tile kt+2 go out right after the barrier.
-    const int nk = nkps * nseg<DT>();
+    const int nk = nkps * (split_a ? 2 : nseg<DT>());
     FV fa0[RM], fb0[RN], fa1[RM], fb1[RN];
     auto read_frag = [&](FV (&fa)[RM], FV (&fb)[RN], int buf, int sidx) {
       const int ch = sidx / SUB, sub = sidx % SUB;

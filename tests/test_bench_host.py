@@ -25,9 +25,11 @@ def test_cpu_baseline_reports_all_and_one_core():
 
 
 def test_traffic_reported_only_for_the_measured_source(tmp_path, monkeypatch):
-    src = json.load(open(bench.TRAFFIC_FILE))
-    key = next(iter(src))
-    per_item = src[key]["bytes_per_item"]
+    import hashlib
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1505_07959_amd", "csrc", "gemm.hip"), "rb").read()).hexdigest()
+    key = "gemm_f64_fine_step_n4096"
+    per_item = 2.5e9
+    src = {key: {"bytes_per_item": per_item, "gemm_sha256": sha}}
     good = tmp_path / "good.json"
     good.write_text(json.dumps(src))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(good))
