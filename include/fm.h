@@ -83,7 +83,8 @@ typedef enum { FM_F64 = 0, FM_F32 = 1, FM_BF16 = 2, FM_F16 = 3, FM_BF16X3 = 4 } 
 /* Coarse propagator G. */
 typedef enum {
   FM_COARSE_EULER = 0,    /* forward Euler steps */
-  FM_COARSE_LEARNED = 1,  /* degree-3 polynomial step X p(K) + q(K), K = h B X,
+  FM_COARSE_LEARNED = 1,  /* degree-3 polynomial step X p(K) + q(K), K =
+                             h (A - I) X (homotopy) or h (A X - I) (X - X A X),
                              coefficients from the loaded network, with a
                              per-slice fallback to Euler (see fm_params)    */
   FM_COARSE_CN = 2        /* Crank-Nicolson steps (linear flows only; see

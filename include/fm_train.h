@@ -4,9 +4,10 @@
  *
  * The classical parareal algorithm (Sec. 2, Alg. 1 of Chehab & Petcu) accepts
  * any cheap coarse propagator G.  The library's learned G is the polynomial
- * step X+ = X p(K) + q(K), K = h B X, B = A - I (inverse homotopy) or A
- * (steady inverse flow X' = X - X A X), p and q cubic with coefficients
- * c = c_Euler(h) + y, where y (8 values) comes from a network of the inputs
+ * step X+ = X p(K) + q(K), K = h (A - I) X (inverse homotopy) or
+ * K = h (A X - I) (steady inverse flow X' = X - X A X, centred on its root),
+ * p and q cubic with coefficients c = c_Euler + y, c_Euler = (1, -1, 0, ...)
+ * (forward Euler), where y (8 values) comes from a network of the inputs
  * x = (t, h, mu_1..mu_4), mu_j = tr((A - I)^j) / n: standardised
  * z = (x - mean) / std, three tanh layers of width 64, linear output.
  * Weights: 9288 values, layer by layer, W (out x in, row-major) then b.
@@ -57,8 +58,8 @@ fm_status fm_mlp_adam(float* theta, const float* grad, float* m, float* v, int64
                       void* hip_stream);
 
 /* Fitting data of the step family for state/target pairs, one per problem b
- * of the flow: the basis E = (X, X K, X K^2, X K^3, I, K, K^2, K^3), K = h B X,
- * built with FP64 products; D = FX - sum_a cE_a E_a (cE: Euler coefficients).
+ * of the flow: the basis E = (X, X K, X K^2, X K^3, I, K, K^2, K^3), K as
+ * above, built with FP64 products; D = FX - sum_a cE_a E_a (cE: Euler coefficients).
  * Row row0 + b of the outputs receives G_ab = <E_a, E_b>_F (64), bD_a =
  * <E_a, D>_F (8), fD = ||D||_F^2 and fn = ||FX||_F^2.  X, FX: host arrays of
  * device n x n FP64 matrices.  Only for the inverse flows. */

@@ -4,13 +4,17 @@ Test infrastructure only.  The paper's Alg. 1 allows any cheap coarse
 propagator G; here G is a degree-3 matrix-polynomial step whose 8 coefficients
 come from a small network.  Reading used (the paper does not define this part):
 
-* Step family.  With K = h B X, B = A - I (HOMOTOPY) or B = A (STEADY_INV),
+* Step family.  With K = h (A - I) X (HOMOTOPY) or K = h (A X - I)
+  (STEADY_INV, centred on the root: K = 0 at X = A^{-1}),
       X+ = X p(K) + q(K),  p(K) = c0 I + c1 K + c2 K^2 + c3 K^3,
                            q(K) = c4 I + c5 K + c6 K^2 + c7 K^3.
-  Forward Euler is the member c = (1, -1, 0, ..., 0) for HOMOTOPY and
-  c = (1 + h, -1, 0, ..., 0) for STEADY_INV; (1, -1, 1, -1, 0, ...) is the
-  third-order Taylor step of the homotopy (its exact one-step map is
-  X (I + K)^{-1}).
+  Forward Euler is the member c = (1, -1, 0, ..., 0) for both flows.  The
+  exact one-step maps are X (I + K)^{-1} (HOMOTOPY) and X (I + g K)^{-1},
+  g = (1 - e^{-h}) / h (STEADY_INV); (1, -1, 1, -1, 0, ...) and
+  (1, -g, g^2, -g^3, 0, ...) are their third-order truncations.  For the
+  steady flow the root-centred K matters: in powers of h A X the exact map's
+  expansion diverges near the root once e^h > 2, in powers of h (A X - I)
+  it converges along the whole path from X0 = I for 0 < A <= I.
 * Network output.  The network emits a correction added to the Euler
   coefficients, so a zero network is Euler.
 * Network inputs: (t, h, mu_1, ..., mu_4), mu_j = tr((A - I)^j) / n,
@@ -24,9 +28,8 @@ come from a small network.  Reading used (the paper does not define this part):
   states that are functions of A the 8 basis matrices are simultaneously
   diagonal, so an unpenalised fit can trade X-terms against K-terms and pick
   huge coefficients that match the trajectory and blow up off it; the exact
-  one-step maps of both flows have the form X p(K) (homotopy:
-  X (I + K)^{-1}; steady inverse: X (e^{-h} I + (1 - e^{-h}) K / h)^{-1}), so
-  the penalty on q costs nothing where the step is right.
+  one-step maps of both flows have the form X p(K), so the penalty on q
+  costs nothing where the step is right.
 * Use in parareal, with the Euler step as fallback: at iteration k, for each
   slice the learned value G_L(U^k_n) is kept if finite and if its defect
   against F(U^k_n) does not exceed Euler's; otherwise Euler is used.  The
@@ -41,8 +44,9 @@ come from a small network.  Reading used (the paper does not define this part):
   counts from the restart.  A non-finite sweep with Euler in use, or one
   that reaches max_iter, ends the run as non-finite.
 
-Parity: pinned by the Euler member reproducing forward Euler, by the Taylor
-member's fourth-order local error against the closed-form homotopy, by the
+Parity: pinned by the Euler member reproducing forward Euler, by the
+truncation members' fourth-order local error against the closed-form maps of
+both flows, by the
 Gram-form defect matching the directly computed defect, by the LS solution
 matching a least-squares solve on the flattened basis, by the per-slice
 choice on scalar problems whose defects have closed forms (learned better on
@@ -59,13 +63,10 @@ from . import integrators
 
 
 def euler_coeffs(kind, h):
-    c = np.zeros(8)
-    if kind == HOMOTOPY:
-        c[0] = 1.0
-    elif kind == STEADY_INV:
-        c[0] = 1.0 + h
-    else:
+    if kind not in (HOMOTOPY, STEADY_INV):
         raise ValueError("learned coarse step defined for the inverse flows only")
+    c = np.zeros(8)
+    c[0] = 1.0
     c[1] = -1.0
     return c
 
@@ -74,12 +75,18 @@ def step_operator(alg, kind, A):
     return shifted(alg, A) if kind == HOMOTOPY else A
 
 
+def step_variable(alg, kind, B, X, h):
+    """K = h B X (HOMOTOPY, B = A - I) or h (B X - I) (STEADY_INV, B = A)."""
+    K = h * alg.mul(B, X)
+    return K if kind == HOMOTOPY else K - h * alg.eye()
+
+
 def poly_step(alg, kind, A, X, h, c, B=None):
-    """One learned step X+ = X p(K) + q(K), K = h B X."""
+    """One learned step X+ = X p(K) + q(K)."""
     if B is None:
         B = step_operator(alg, kind, A)
     I = alg.eye()
-    K = h * alg.mul(B, X)
+    K = step_variable(alg, kind, B, X, h)
     K2 = alg.mul(K, K)
     K3 = alg.mul(K2, K)
     P = c[0] * I + c[1] * K + c[2] * K2 + c[3] * K3
@@ -90,7 +97,7 @@ def poly_step(alg, kind, A, X, h, c, B=None):
 def basis(alg, kind, A, X, h):
     B = step_operator(alg, kind, A)
     I = alg.eye()
-    K = h * alg.mul(B, X)
+    K = step_variable(alg, kind, B, X, h)
     K2 = alg.mul(K, K)
     K3 = alg.mul(K2, K)
     return [X, alg.mul(X, K), alg.mul(X, K2), alg.mul(X, K3), I, K, K2, K3]

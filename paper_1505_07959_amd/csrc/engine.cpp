@@ -649,13 +649,14 @@ static GItem blank_item(const Inst& in, int i) {
 // launch, out = s0 (B_hi Y + B_lo Y) with one FP32 accumulation: B carries
 // 2 x 8 (or 2 x 11) significant bits.
 static void first_product(std::vector<GItem>& items, std::vector<int>& ii, const Inst& in, int i,
-                          const void* b, bool split, const void* y, void* out, double s0) {
+                          const void* b, bool split, const void* y, void* out, double s0, double s2 = 0.0) {
   GItem g = blank_item(in, i);
   g.a = b;
   g.b = y;
   g.out0 = out;
   g.flags = F_E_NONE | (split ? F_SPLIT_A : 0);
   g.s[0] = s0;
+  g.s[2] = s2;  // identity term on the leading n x n diagonal
   items.push_back(g);
   ii.push_back(i);
 }
@@ -1066,7 +1067,9 @@ fm_status Flow::run_coarse(const std::vector<CoarseSlot>& slots, int steps, hipS
         // K = h B Y ; K2 = K K ; P = c0 I + c1 K + c2 K2 + c3 K2 K (and K3) ;
         // X+ = Y P + c4 I + c5 K + c6 K2 + c7 K3
         const double* c = sl.coef + 8 * j;
-        first_product(l1, i1, in, sl.inst, cbop(in), csplit(in), yin, sl.k1, sl.h);
+        // K = h (A - I) Y (homotopy) or h (A Y - I) (X - X A X, centred on the root)
+        first_product(l1, i1, in, sl.inst, cbop(in), csplit(in), yin, sl.k1, sl.h,
+                      in.kind == FM_FLOW_INV_STEADY ? -sl.h : 0.0);
         GItem g2 = blank_item(in, sl.inst);
         g2.a = sl.k1;
         g2.b = sl.k1;
@@ -2432,9 +2435,13 @@ fm_status Flow::refine(const std::vector<int>& which, std::vector<double*>& X, c
   return FM_OK;
 }
 
+// Forward Euler in the learned step family: X+ = X (I - K) for both flows
+// (K = h (A - I) X for the homotopy, h (A X - I) for X - X A X).
 void euler_coeffs(int kind, double h, double* c) {
+  (void)kind;
+  (void)h;
   for (int q = 0; q < 8; ++q) c[q] = 0.0;
-  c[0] = kind == FM_FLOW_INV_STEADY ? 1.0 + h : 1.0;
+  c[0] = 1.0;
   c[1] = -1.0;
 }
 
@@ -2610,7 +2617,12 @@ fm_status Flow::features(double h, const double* const* X, const double* const* 
       g.s[0] = scale;
       g.flags = F_OUT0_F64 | F_E_NONE;
       switch (which) {
-        case 0: g.a = b[i].B; g.b = b[i].x; g.out0 = b[i].k[0]; break;      // K = h B X
+        case 0:  // K = h (A - I) X, or h (A X - I) for X - X A X
+          g.a = b[i].B;
+          g.b = b[i].x;
+          g.out0 = b[i].k[0];
+          if (inst[i].kind == FM_FLOW_INV_STEADY) g.s[2] = -scale;
+          break;
         case 1: g.a = b[i].k[0]; g.b = b[i].k[0]; g.out0 = b[i].k[1]; break;  // K^2
         case 2: g.a = b[i].k[1]; g.b = b[i].k[0]; g.out0 = b[i].k[2]; break;  // K^3
         default: g.a = b[i].x; g.b = b[i].k[which - 3]; g.out0 = b[i].xk[which - 3];  // X K^j

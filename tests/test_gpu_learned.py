@@ -188,17 +188,44 @@ def test_training_pipeline_small(tmp_path):
         fm.fm_destroy(flow)
 
 
+def _rebase_to_root_centred(theta, h):
+    """A network written for the step variable K' = h A X (the fixture below
+    was trained with it) re-expressed for K = h (A X - I) = K' - h I at one
+    step size h: a cubic in K' is the cubic in K with coefficients
+    a_i = sum_{j >= i} binom(j, i) h^(j-i) a'_j (for p and for q alike).  The
+    map T is linear and maps the old Euler member (1 + h, -1, 0, ...) to the
+    new one (1, -1, 0, ...), so only the output layer changes: W4 <- T W4,
+    b4 <- T b4."""
+    from math import comb
+    Tm = np.zeros((8, 8))
+    for half in (0, 4):
+        for i in range(4):
+            for jj in range(i, 4):
+                Tm[half + i, half + jj] = comb(jj, i) * h ** (jj - i)
+    th = theta.copy()
+    nw4 = 8 * 64
+    W4 = th[-(nw4 + 8):-8].reshape(8, 64)
+    th[-(nw4 + 8):-8] = (Tm @ W4).ravel()
+    th[-8:] = Tm @ th[-8:]
+    return th
+
+
 def test_learned_restart_matches_oracle():
-    """The restart path: the trained steady-flow network on X' = X - X A X
-    (n = 256, lam ~ loguniform[1e-3, 1], N = 32 over [0, 30], 16 RK4 steps
-    per slice, FP64) overflows in its first sweep, in the oracle as on the
-    GPU; both restart from Step 0 with Euler, count the failed iteration, and
-    agree on every later increment and on the result."""
+    """The restart path, in a case where it happens by itself: a network
+    trained for X' = X - X A X with the step variable h A X (fixture
+    tests/golden/steady_k_basis_n256.fmw, trained by this project's
+    train_coarse before the root-centred variable; re-expressed exactly for
+    the library's K = h (A X - I), same steps), n = 256, lam ~
+    loguniform[1e-3, 1], N = 32 over [0, 30], 16 RK4 steps per slice, FP64.
+    Its polynomial cannot follow the flow's step at h = 30/32, the first
+    sweep overflows in the oracle as on the GPU; both restart from Step 0
+    with Euler, count the failed iteration, and agree on every later
+    increment and on the result."""
     from paper_1505_07959_amd import fm, train_coarse
-    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1505_07959_amd",
-                        "models", "steady_n256.fmw")
-    kind, theta, norm = train_coarse.read_model(path)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "steady_k_basis_n256.fmw")
+    kind, theta0, norm = train_coarse.read_model(path)
     n, N, S, T, K, tol = 256, 32, 16, 30.0, 32, 1e-8
+    theta = _rebase_to_root_centred(theta0, T / N)
     A, Q, lam = inputs.spd(n, "loguniform", 1e-3, 1.0, 57, scale_to_unit=True)
     mu = [np.mean((lam - 1) ** j) for j in (1, 2, 3, 4)]
 
@@ -210,8 +237,9 @@ def test_learned_restart_matches_oracle():
     with np.errstate(all="ignore"):
         ref = learned.parareal_learned(salg, STEADY_INV, lam, salg.eye(), T, N, 1, S, K, tol, coeff)
     assert ref["restarts"] == 1 and ref["status"] == "ok"
-    flow = fm.fm_flow_create([(STEADY_INV, dev(A))], "f64", "coarse_model=" + path)
+    flow = fm.fm_flow_create([(STEADY_INV, dev(A))], "f64")
     try:
+        fm.fm_flow_set_coarse_model(flow, STEADY_INV, theta, norm)
         out = empty(n)
         st, stats = fm.fm_parareal_solve(flow, None, [out], [{"T": T, "N": N, "fine_steps": S, "max_iter": K,
                                                               "tol": tol, "coarse": fm.FM_COARSE_LEARNED}])

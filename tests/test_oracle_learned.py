@@ -240,3 +240,31 @@ def test_restart_after_a_nonfinite_sweep_is_plain_euler_parareal():
     one = learned.parareal_learned(alg, HOMOTOPY, lam, alg.eye(), 1.0, N, 1, S, 1, tol, lambda tt, h: taylor,
                                    fine=failing_fine)
     assert one["status"] == "nonfinite" and one["iters"] == 1 and one["restarts"] == 0
+
+
+def test_steady_truncation_member_fourth_order_local_error():
+    """For X' = X - X A X with K = h (A X - I) the exact one-step map is
+    X (I + g K)^{-1}, g = (1 - e^{-h}) / h (from the closed form of the flow);
+    the member (1, -g, g^2, -g^3, 0, ...) is its third-order truncation: local
+    error O(h^4) against the closed form, from a start away from the root."""
+    A, _, _ = inputs.spd(6, "uniform", 0.3, 1.0, 25)
+    X = 0.6 * inputs.perturbed_identity(6, 26, 0.1)
+    alg = MatrixAlgebra(6)
+    errs = []
+    for h in (0.1, 0.05, 0.025):
+        g = (1 - np.exp(-h)) / h
+        c = np.array([1.0, -g, g * g, -g ** 3, 0, 0, 0, 0])
+        ex = exact.closed_form(STEADY_INV, A, X, h)
+        errs.append(np.linalg.norm(learned.poly_step(alg, STEADY_INV, A, X, h, c) - ex))
+    assert 14 < errs[0] / errs[1] < 18 and 14 < errs[1] / errs[2] < 18
+
+
+def test_steady_step_variable_vanishes_at_the_root():
+    """K = h (A X - I) is zero at X = A^{-1}: every member with c0 = 1 and
+    q(0) = c4 = 0 keeps the root fixed."""
+    A, _, _ = inputs.spd(5, "uniform", 0.3, 1.0, 27)
+    Ainv = exact.inverse_lu(A)
+    alg = MatrixAlgebra(5)
+    c = np.array([1.0, -0.7, 0.3, -0.1, 0.0, 0.2, -0.05, 0.01])
+    X = learned.poly_step(alg, STEADY_INV, A, Ainv, 0.9, c)
+    assert np.linalg.norm(X - Ainv) <= 1e-13 * np.linalg.norm(Ainv)
