@@ -293,49 +293,64 @@ __device__ __forceinline__ void epilogue4(const GItem& it, int64_t idx, int dpos
   }
 }
 
-// The same epilogue split in two phases, used for the 16-bit products
-// whose epilogue is bound by memory latency: a thread issues the global
-// loads of several element groups (epi_load) before it combines any of them
-// with the products and stores (epi_apply).  The affine product and the RK4
-// stage update run in FP32, on an FP32 state (F_X_F32): the product is
-// itself an FP32 accumulation of 16-bit operands, and FP32 keeps everything
-// such a step produces.  The Euler update (FP64 state) and every FP64 output
-// stay in FP64.  The identity term touches one element of the
-// diagonal tiles only, so it sits behind a branch that other groups skip.
+// The epilogue of the 16-bit products, split in two phases: a thread issues
+// the global loads of the element groups of the next round (epi_load)
+// before it combines the current ones with the products and stores them
+// (epi_apply).  Every access goes through a buffer resource over what the
+// output tile touches of its matrix, rebased to the tile's first element;
+// an operand that an item does not have (the accumulator of RK4 stage 1)
+// gets an empty range, so its loads return zeros and no load sits behind a
+// branch.  A branch around a load would make the compiler wait for that
+// load where the paths merge, and since loads and stores share one
+// in-order counter, every such wait would also wait for all stores issued
+// before it.  The loaded values stay raw (operand type) until epi_apply.
+// The affine product and the RK4 stage update run in FP32, on an FP32
+// state (F_X_F32): the product is itself an FP32 accumulation of 16-bit
+// operands, and FP32 keeps everything such a step produces.  The Euler
+// update (FP64 state) and every FP64 output stay in FP64.  The identity
+// term touches one element of the diagonal tiles only, so it sits behind a
+// branch that other groups skip.
 typedef float f4v __attribute__((ext_vector_type(EV)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
 
+// Resource over `extent` elements of `esz` bytes from element `off` of p;
+// an absent operand gets zero records.
+__device__ __forceinline__ rsrc_t tile_rsrc(const void* p, int64_t off, int esz, int64_t extent, bool present) {
+  char* base = present ? (char*)p + off * esz : (char*)p;
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, present ? (int)(extent * esz) : 0, 0x00020000);
+}
+// four consecutive elements at element offset `off`
+__device__ __forceinline__ f4v bld_f32(rsrc_t r, int off) {
+  return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, off * 4, 0, 0));
+}
+__device__ __forceinline__ d4 bld_f64(rsrc_t r, int off) {
+  const d2 lo = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off * 8, 0, 0));
+  const d2 hi = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off * 8 + 16, 0, 0));
+  return d4{lo.x, lo.y, hi.x, hi.y};
+}
 template <class T>
-__device__ __forceinline__ f4v gld4f(const void* p, int64_t idx) {
-  const vec4<T> w = *(gptr<vec4<T>>)((const T*)p + idx);
+__device__ __forceinline__ vec4<T> bld_16(rsrc_t r, int off) {
+  return __builtin_bit_cast(vec4<T>, __builtin_amdgcn_raw_buffer_load_b64(r, off * 2, 0, 0));
+}
+__device__ __forceinline__ void bst_f32(rsrc_t r, int off, f4v x) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, x), r, off * 4, 0, 0);
+}
+__device__ __forceinline__ void bst_f64(rsrc_t r, int off, const V4& x) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, d2{x.v[0], x.v[1]}), r, off * 8, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, d2{x.v[2], x.v[3]}), r, off * 8 + 16, 0, 0);
+}
+template <class T>
+__device__ __forceinline__ void bst_16(rsrc_t r, int off, vec4<T> w) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, w), r, off * 2, 0, 0);
+}
+template <class T>
+__device__ __forceinline__ f4v widen16(vec4<T> w) {
   f4v r;
 #pragma unroll
   for (int e = 0; e < EV; ++e) r[e] = (float)w[e];
   return r;
-}
-__device__ __forceinline__ void gst4f(void* p, int64_t idx, f4v x) {
-  *(gptr_mut<f4v>)((float*)p + idx) = x;
-}
-template <int DT>
-__device__ __forceinline__ f4v ld_op4f(const void* p, int64_t idx, int64_t np2) {
-  using T = typename Tr<DT>::T;
-  f4v r = gld4f<T>(p, idx);
-  if constexpr (DT == DT_BF16X3) r += gld4f<T>(p, idx + np2);
-  return r;
-}
-// split BF16: hi = bf16(v), lo = bf16(v - hi); v - hi is exact in FP32
-template <int DT>
-__device__ __forceinline__ void st_op4f(void* p, int64_t idx, int64_t np2, f4v x) {
-  using T = typename Tr<DT>::T;
-  vec4<T> w;
-#pragma unroll
-  for (int e = 0; e < EV; ++e) w[e] = (T)x[e];
-  *(gptr_mut<vec4<T>>)((T*)p + idx) = w;
-  if constexpr (DT == DT_BF16X3) {
-    vec4<T> lo;
-#pragma unroll
-    for (int e = 0; e < EV; ++e) lo[e] = (T)(x[e] - (float)w[e]);
-    *(gptr_mut<vec4<T>>)((T*)p + idx + np2) = lo;
-  }
 }
 __device__ __forceinline__ V4 widen(f4v a) {
   V4 r;
@@ -358,114 +373,213 @@ __device__ __forceinline__ void add_diag(V4& v, int dpos, double d) {
   }
 }
 
+// Operand-type matrices as (hi, lo) planes: split BF16 stores hi = bf16(v)
+// and lo = bf16(v - hi) in the second plane (pl = np^2 elements further) and
+// reads back hi + lo; the other types have one plane.
+template <int DT>
+struct Op4 {
+  vec4<typename Tr<DT>::T> w[DT == DT_BF16X3 ? 2 : 1];
+};
+template <int DT>
+__device__ __forceinline__ Op4<DT> bld_op(rsrc_t r, int off, int pl) {
+  using T = typename Tr<DT>::T;
+  Op4<DT> o;
+  o.w[0] = bld_16<T>(r, off);
+  if constexpr (DT == DT_BF16X3) o.w[1] = bld_16<T>(r, off + pl);
+  return o;
+}
+template <int DT>
+__device__ __forceinline__ f4v op_f32(const Op4<DT>& o) {  // hi + lo in FP32
+  f4v r = widen16(o.w[0]);
+  if constexpr (DT == DT_BF16X3) r += widen16(o.w[1]);
+  return r;
+}
+template <int DT>
+__device__ __forceinline__ V4 op_f64(const Op4<DT>& o) {  // hi + lo in FP64
+  V4 r;
+#pragma unroll
+  for (int e = 0; e < EV; ++e) r.v[e] = from_op(o.w[0][e]);
+  if constexpr (DT == DT_BF16X3) {
+#pragma unroll
+    for (int e = 0; e < EV; ++e) r.v[e] += from_op(o.w[1][e]);
+  }
+  return r;
+}
+template <int DT>
+__device__ __forceinline__ void bst_op(rsrc_t r, int off, int pl, f4v x) {  // from FP32
+  using T = typename Tr<DT>::T;
+  vec4<T> w;
+#pragma unroll
+  for (int e = 0; e < EV; ++e) w[e] = (T)x[e];
+  bst_16<T>(r, off, w);
+  if constexpr (DT == DT_BF16X3) {  // x - hi is exact in FP32
+    vec4<T> lo;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) lo[e] = (T)(x[e] - (float)w[e]);
+    bst_16<T>(r, off + pl, lo);
+  }
+}
+template <int DT>
+__device__ __forceinline__ void bst_op(rsrc_t r, int off, int pl, const V4& x) {  // from FP64
+  using T = typename Tr<DT>::T;
+  vec4<T> w;
+#pragma unroll
+  for (int e = 0; e < EV; ++e) w[e] = to_op<T>(x.v[e]);
+  bst_16<T>(r, off, w);
+  if constexpr (DT == DT_BF16X3) {
+    vec4<T> lo;
+#pragma unroll
+    for (int e = 0; e < EV; ++e) lo[e] = to_op<T>(x.v[e] - from_op<T>(w[e]));
+    bst_16<T>(r, off + pl, lo);
+  }
+}
+
+// Resources of one output tile's epilogue.  E (in0) is FP64 or of operand
+// type; the kernel picks the epilogue body by the item's E mode EM
+// (0 none, 1 FP64, 2 operand type), so only the loads of that mode exist.
+struct EpiRs {
+  rsrc_t e64, eop;       // E: FP64, operand type
+  rsrc_t x, kq;          // RK4: FP32 state, FP32 stage accumulator (stage >= 2); Euler: FP64 state
+  rsrc_t i1, i2;         // POLYP/POLYX inputs (operand type); POLY* take in0 from eop
+  rsrc_t o0d, o0t;       // out0 as FP64 / operand type
+  rsrc_t o1;             // out1 (RK4: FP32, Euler and POLYX: FP64, POLYP: operand type)
+  int pl;                // plane offset (elements) of split BF16 operands
+};
+template <int DT, int EPI>
+__device__ __forceinline__ EpiRs epi_rsrc(const GItem& it, int row0, int col0, int bm, int bn) {
+  using T = typename Tr<DT>::T;
+  constexpr int TS = (int)sizeof(T);
+  const int64_t np = it.np, np2 = np * np;
+  const int64_t off = (int64_t)row0 * np + col0;
+  const int64_t ext = (int64_t)(bm - 1) * np + bn;              // one plane
+  const int64_t ext_op = (DT == DT_BF16X3 ? np2 : 0) + ext;     // all planes of an operand-type matrix
+  const bool has_e = !(it.flags & F_E_NONE), e_f64 = (it.flags & F_E_F64) != 0;
+  const bool poly = EPI == EPI_POLYP || EPI == EPI_POLYX;
+  EpiRs r;
+  r.pl = DT == DT_BF16X3 ? (int)np2 : 0;
+  r.e64 = tile_rsrc(it.in0, off, 8, ext, !poly && has_e && e_f64);
+  r.eop = tile_rsrc(it.in0, off, TS, ext_op, poly || (has_e && !e_f64));
+  r.x = EPI == EPI_EULER ? tile_rsrc(it.x, off, 8, ext, true) : tile_rsrc(it.x, off, 4, ext, EPI == EPI_RK4);
+  r.kq = tile_rsrc(it.out1, off, 4, ext, EPI == EPI_RK4 && it.stage >= 2);
+  r.i1 = tile_rsrc(it.in1, off, TS, ext_op, poly);
+  r.i2 = tile_rsrc(it.in2, off, TS, ext_op, EPI == EPI_POLYX);
+  const bool o0_f64 = EPI == EPI_AFFINE && (it.flags & F_OUT0_F64);
+  r.o0d = tile_rsrc(it.out0, off, 8, ext, o0_f64);
+  r.o0t = tile_rsrc(it.out0, off, TS, ext_op, !o0_f64);
+  const int o1sz = EPI == EPI_RK4 ? 4 : EPI == EPI_POLYP ? TS : 8;
+  r.o1 = tile_rsrc(it.out1, off, o1sz, EPI == EPI_POLYP ? ext_op : ext, EPI != EPI_AFFINE);
+  return r;
+}
+
+template <int DT>
 struct EpiIn {
-  V4 p, q, r;  // FP64: Euler state, POLYP/POLYX inputs, E of an FP64 output
-  f4v kq, er;  // FP32: RK4 stage accumulator, E
-  f4v xf;      // FP32 RK4 state (F_X_F32)
+  d4 e64;        // E (EM 1); Euler: FP64 state in xd
+  Op4<DT> eop;   // E (EM 2); POLYP/POLYX: in0
+  Op4<DT> i1, i2;
+  f4v xf, kq;    // RK4 FP32 state and stage accumulator
+  d4 xd;         // Euler FP64 state
 };
 
-template <int DT, int EPI>
-__device__ __forceinline__ EpiIn epi_load(const GItem& it, int64_t idx) {
-  const int64_t np2 = (int64_t)it.np * it.np;
-  EpiIn in;
-  auto load_e = [&]() -> V4 {
-    return (it.flags & F_E_F64) ? gld4<double>(it.in0, idx) : ld_op4<DT>(it.in0, idx, np2);
-  };
-  auto load_ef = [&]() -> f4v {
-    return (it.flags & F_E_F64) ? gld4f<double>(it.in0, idx) : ld_op4f<DT>(it.in0, idx, np2);
-  };
-  if constexpr (EPI == EPI_AFFINE) {
-    if (!(it.flags & F_E_NONE)) {
-      if (it.flags & F_OUT0_F64) in.r = load_e();
-      else in.er = load_ef();
-    }
-  } else if constexpr (EPI == EPI_RK4) {
-    if (!(it.flags & F_E_NONE)) in.er = load_ef();
-    in.xf = gld4f<float>(it.x, idx);  // 16-bit products: FP32 state (F_X_F32)
-    if (it.stage >= 2) in.kq = gld4f<float>(it.out1, idx);
+template <int DT, int EPI, int EM>
+__device__ __forceinline__ EpiIn<DT> epi_load(const EpiRs& rs, int off) {
+  EpiIn<DT> in;
+  if constexpr (EM == 1) in.e64 = bld_f64(rs.e64, off);
+  if constexpr (EM == 2 || EPI == EPI_POLYP || EPI == EPI_POLYX) in.eop = bld_op<DT>(rs.eop, off, rs.pl);
+  if constexpr (EPI == EPI_RK4) {
+    in.xf = bld_f32(rs.x, off);
+    in.kq = bld_f32(rs.kq, off);  // zeros at stage 1 (empty range)
   } else if constexpr (EPI == EPI_EULER) {
-    if (!(it.flags & F_E_NONE)) in.r = load_e();
-    in.p = gld4<double>(it.x, idx);
-  } else if constexpr (EPI == EPI_POLYP) {
-    in.p = ld_op4<DT>(it.in0, idx, np2);
-    in.q = ld_op4<DT>(it.in1, idx, np2);
-  } else {
-    in.p = ld_op4<DT>(it.in0, idx, np2);
-    in.q = ld_op4<DT>(it.in1, idx, np2);
-    in.r = ld_op4<DT>(it.in2, idx, np2);
+    in.xd = bld_f64(rs.x, off);
+  } else if constexpr (EPI == EPI_POLYP || EPI == EPI_POLYX) {
+    in.i1 = bld_op<DT>(rs.i1, off, rs.pl);
+    if constexpr (EPI == EPI_POLYX) in.i2 = bld_op<DT>(rs.i2, off, rs.pl);
   }
   return in;
 }
 
+__device__ __forceinline__ V4 to_v4(d4 d) { return V4{{d.x, d.y, d.z, d.w}}; }
+
 // af: the four FP32 accumulations of the product
-template <int DT, int EPI>
-__device__ __forceinline__ void epi_apply(const GItem& it, int64_t idx, int dpos, const f4v& af, const EpiIn& in) {
+template <int DT, int EPI, int EM>
+__device__ __forceinline__ void epi_apply(const GItem& it, const EpiRs& rs, int off, int dpos, const f4v& af,
+                                          const EpiIn<DT>& in) {
   static_assert(std::is_same<typename Tr<DT>::Acc, float>::value, "16-bit products accumulate in FP32");
   const double* s = it.s;
-  const int64_t np2 = (int64_t)it.np * it.np;
+  // E in FP32 / FP64 (EM 0: no E term)
+  auto e32 = [&]() -> f4v {
+    if constexpr (EM == 1) return __builtin_convertvector(in.e64, f4v);
+    else return op_f32<DT>(in.eop);
+  };
+  auto e64 = [&]() -> V4 {
+    if constexpr (EM == 1) return to_v4(in.e64);
+    else return op_f64<DT>(in.eop);
+  };
   if constexpr (EPI == EPI_AFFINE) {
     if (it.flags & F_OUT0_F64) {
       const V4 a = widen(af);
       V4 v;
 #pragma unroll
       for (int e = 0; e < EV; ++e) v.v[e] = s[0] * a.v[e];
-      if (!(it.flags & F_E_NONE)) {
+      if constexpr (EM != 0) {
+        const V4 ev = e64();
 #pragma unroll
-        for (int e = 0; e < EV; ++e) v.v[e] += s[1] * in.r.v[e];
+        for (int e = 0; e < EV; ++e) v.v[e] += s[1] * ev.v[e];
       }
       add_diag(v, dpos, s[2]);
-      gst4<double>(it.out0, idx, v);
+      bst_f64(rs.o0d, off, v);
     } else {
       f4v v = (float)s[0] * af;
-      if (!(it.flags & F_E_NONE)) v += (float)s[1] * in.er;
+      if constexpr (EM != 0) v += (float)s[1] * e32();
       add_diag(v, dpos, (float)s[2]);
-      st_op4f<DT>(it.out0, idx, np2, v);
+      bst_op<DT>(rs.o0t, off, rs.pl, v);
     }
   } else if constexpr (EPI == EPI_RK4) {
     f4v k = (float)s[0] * af;
-    if (!(it.flags & F_E_NONE)) k += (float)s[1] * in.er;
+    if constexpr (EM != 0) k += (float)s[1] * e32();
     if (s[3] != 0.0) add_diag(k, dpos, (float)s[3]);  // identity term of the field (dX/dt = I - A X)
     // the state of a fine solve with 16-bit products is FP32 (F_X_F32)
     const double h = s[2];
     if (it.stage == 4) {  // X <- X + h/6 (k1 + 2 k2 + 2 k3 + k4)
       const f4v o = in.xf + (float)(h / 6.0) * (in.kq + k);
-      gst4f(it.x, idx, o);
-      st_op4f<DT>(it.out0, idx, np2, o);
+      bst_f32(rs.x, off, o);
+      bst_op<DT>(rs.o0t, off, rs.pl, o);
     } else {
-      gst4f(it.out1, idx, it.stage == 1 ? k : in.kq + 2.0f * k);
-      st_op4f<DT>(it.out0, idx, np2, in.xf + (float)(it.stage == 3 ? h : 0.5 * h) * k);
+      bst_f32(rs.o1, off, it.stage == 1 ? k : in.kq + 2.0f * k);
+      bst_op<DT>(rs.o0t, off, rs.pl, in.xf + (float)(it.stage == 3 ? h : 0.5 * h) * k);
     }
   } else if constexpr (EPI == EPI_EULER) {
     const V4 a = widen(af);
     V4 k;
 #pragma unroll
     for (int e = 0; e < EV; ++e) k.v[e] = s[0] * a.v[e];
-    if (!(it.flags & F_E_NONE)) {
+    if constexpr (EM != 0) {
+      const V4 ev = e64();
 #pragma unroll
-      for (int e = 0; e < EV; ++e) k.v[e] += s[1] * in.r.v[e];
+      for (int e = 0; e < EV; ++e) k.v[e] += s[1] * ev.v[e];
     }
     if (s[3] != 0.0) add_diag(k, dpos, s[3]);
+    const V4 p = to_v4(in.xd);
     V4 o;
 #pragma unroll
-    for (int e = 0; e < EV; ++e) o.v[e] = in.p.v[e] + s[2] * k.v[e];
-    gst4<double>(it.out1, idx, o);
-    st_op4<DT>(it.out0, idx, np2, o);
+    for (int e = 0; e < EV; ++e) o.v[e] = p.v[e] + s[2] * k.v[e];
+    bst_f64(rs.o1, off, o);
+    bst_op<DT>(rs.o0t, off, rs.pl, o);
   } else if constexpr (EPI == EPI_POLYP) {
-    const V4 a = widen(af);
+    const V4 a = widen(af), p = op_f64<DT>(in.eop), q = op_f64<DT>(in.i1);
     V4 v;
 #pragma unroll
-    for (int e = 0; e < EV; ++e) v.v[e] = s[1] * in.p.v[e] + s[2] * in.q.v[e] + s[3] * a.v[e];
+    for (int e = 0; e < EV; ++e) v.v[e] = s[1] * p.v[e] + s[2] * q.v[e] + s[3] * a.v[e];
     add_diag(v, dpos, s[0]);
-    st_op4<DT>(it.out0, idx, np2, v);
-    st_op4<DT>(it.out1, idx, np2, a);
+    bst_op<DT>(rs.o0t, off, rs.pl, v);
+    bst_op<DT>(rs.o1, off, rs.pl, a);
   } else {  // EPI_POLYX
-    const V4 a = widen(af);
+    const V4 a = widen(af), p = op_f64<DT>(in.eop), q = op_f64<DT>(in.i1), r = op_f64<DT>(in.i2);
     V4 v;
 #pragma unroll
-    for (int e = 0; e < EV; ++e) v.v[e] = a.v[e] + s[5] * in.p.v[e] + s[6] * in.q.v[e] + s[7] * in.r.v[e];
+    for (int e = 0; e < EV; ++e) v.v[e] = a.v[e] + s[5] * p.v[e] + s[6] * q.v[e] + s[7] * r.v[e];
     add_diag(v, dpos, s[4]);
-    gst4<double>(it.out1, idx, v);
-    st_op4<DT>(it.out0, idx, np2, v);
+    bst_f64(rs.o1, off, v);
+    bst_op<DT>(rs.o0t, off, rs.pl, v);
   }
 }
 
@@ -917,13 +1031,11 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
       static_assert(CROWS * CLD * (int)sizeof(Acc) <= SMEM, "epilogue staging must fit in LDS");
       Acc* Cs = reinterpret_cast<Acc*>(smem);
       const int n_valid = it.n;
-      // ITER element groups per thread and pass, handled EG at a time
+      // ITER element groups per thread and pass
       constexpr int ITER = CROWS * BN / EV / NT;
-      constexpr int EG = (DT == DT_F64 || DT == DT_F32) ? 1 : (ITER < 2 ? ITER : 2);
-      static_assert(CROWS * BN / EV % NT == 0 && ITER % EG == 0, "epilogue split");
-#pragma unroll
-      for (int i = 0; i < RM; ++i) {
-        epi_sync(std::integral_constant<bool, (EG > 1)>());  // K loop / previous pass readers are done with LDS
+      static_assert(CROWS * BN / EV % NT == 0, "epilogue split");
+      auto stage_acc = [&](auto i_c) {
+        constexpr int i = decltype(i_c)::value;
 #pragma unroll
         for (int j = 0; j < RN; ++j)
 #pragma unroll
@@ -932,8 +1044,13 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
             acc_pos<DT>(lane, v, r, c);
             Cs[(wr * MI + r) * CLD + wc * WN + j * MI + c] = (Acc)acc[i][j][v];
           }
-        epi_sync(std::integral_constant<bool, (EG > 1)>());
-        if constexpr (EG == 1) {
+      };
+      if constexpr (DT == DT_F64 || DT == DT_F32) {
+        static_for(std::make_integer_sequence<int, RM>(), [&](auto i_c) {
+          constexpr int i = decltype(i_c)::value;
+          __syncthreads();  // K loop / previous pass readers are done with LDS
+          stage_acc(i_c);
+          __syncthreads();
           for (int e = tid; e < CROWS * BN / EV; e += NT) {
             const int rr = (e * EV) / BN, cc = (e * EV) % BN;
             const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
@@ -944,39 +1061,69 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
             const int dpos = (gr >= gc && gr < gc + EV && gr < n_valid) ? gr - gc : -1;
             epilogue4<DT, EPI>(it, (int64_t)gr * np + gc, dpos, a);
           }
-        } else {
-          // ITER / EG rounds; the loads of round r+1 are issued before the
-          // stores of round r: loads and stores share one in-order counter,
-          // so waiting for loads issued after a store waits for that store
-          constexpr int ROUNDS = ITER / EG;
-          EpiIn in[2][EG];
-          int64_t idx[2][EG];
-          auto load_round = [&](int r, auto b_c) {
-            constexpr int b = decltype(b_c)::value;
+        });
+      } else {
+        // 16-bit products: EG element groups per round, ROUNDS rounds per
+        // pass; the loads of round R+1 (of the next pass, at a pass's last
+        // round) are issued before the stores of round R.
+        constexpr int EG = ITER < 2 ? ITER : 2;
+        static_assert(ITER % EG == 0, "epilogue split");
+        constexpr int ROUNDS = ITER / EG;
+        constexpr int NR = RM * ROUNDS;
+        const EpiRs rs = epi_rsrc<DT, EPI>(it, row0, col0, BM, BN);
+        // Group m = round * EG + g of a pass covers staged row rr0 + m * RS,
+        // columns cc .. cc+3 (the same for every group of a thread), so all
+        // offsets are one per-thread base plus compile-time multiples:
+        // staged row rr0 + m RS is tile row rr0 + trow(pass, m), as RS
+        // divides MI.
+        constexpr int GPR = BN / EV;  // element groups per staged row
+        constexpr int RS = NT / GPR;  // staged rows per sweep of the threads
+        static_assert(NT % GPR == 0 && MI % RS == 0, "epilogue group layout");
+        const int cc = (tid % GPR) * EV, rr0 = tid / GPR;
+        const int gbase = rr0 * np + cc;             // tile-relative element offset
+        const int lbase = rr0 * CLD + cc;            // staged element
+        const int dbase = row0 + rr0 - (col0 + cc);  // row minus column, before trow
+        const int rmax = n_valid - (row0 + rr0);     // diagonal terms only for trow < rmax
+        auto body = [&](auto em_c) {
+          constexpr int EM = decltype(em_c)::value;
+          EpiIn<DT> in[2][EG];
+          auto load_round = [&](auto r_c) {
+            constexpr int R = decltype(r_c)::value;
+            constexpr int i = R / ROUNDS;
 #pragma unroll
             for (int g = 0; g < EG; ++g) {
-              const int e = tid + (r * EG + g) * NT;
-              const int rr = (e * EV) / BN, cc = (e * EV) % BN;
-              const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
-              idx[b][g] = (int64_t)gr * np + col0 + cc;
-              in[b][g] = epi_load<DT, EPI>(it, idx[b][g]);
+              const int m = (R % ROUNDS) * EG + g;
+              const int trow = (m * RS / MI) * WM + i * MI + (m * RS) % MI;
+              in[R & 1][g] = epi_load<DT, EPI, EM>(rs, gbase + trow * np);
             }
           };
-          load_round(0, std::integral_constant<int, 0>());
-          static_for(std::make_integer_sequence<int, ROUNDS>(), [&](auto r_c) {
-            constexpr int r = decltype(r_c)::value;
-            if constexpr (r + 1 < ROUNDS) load_round(r + 1, std::integral_constant<int, (r + 1) & 1>());
+          load_round(std::integral_constant<int, 0>());
+          static_for(std::make_integer_sequence<int, RM>(), [&](auto i_c) {
+            constexpr int i = decltype(i_c)::value;
+            epi_sync(std::true_type());  // K loop / previous pass readers are done with LDS
+            stage_acc(i_c);
+            epi_sync(std::true_type());
+            static_for(std::make_integer_sequence<int, ROUNDS>(), [&](auto r_c) {
+              constexpr int R = i * ROUNDS + decltype(r_c)::value;
+              if constexpr (R + 1 < NR) load_round(std::integral_constant<int, R + 1>());
 #pragma unroll
-            for (int g = 0; g < EG; ++g) {
-              const int e = tid + (r * EG + g) * NT;
-              const int rr = (e * EV) / BN, cc = (e * EV) % BN;
-              const int gr = row0 + (rr / MI) * WM + i * MI + (rr % MI);
-              const int gc = col0 + cc;
-              const f4v af = *(const f4v*)&Cs[rr * CLD + cc];
-              const int dpos = (gr >= gc && gr < gc + EV && gr < n_valid) ? gr - gc : -1;
-              epi_apply<DT, EPI>(it, idx[r & 1][g], dpos, af, in[r & 1][g]);
-            }
+              for (int g = 0; g < EG; ++g) {
+                const int m = decltype(r_c)::value * EG + g;
+                const int trow = (m * RS / MI) * WM + i * MI + (m * RS) % MI;
+                const f4v af = *(const f4v*)&Cs[lbase + m * RS * CLD];
+                const int d = dbase + trow;
+                const int dpos = (d >= 0 && d < EV && trow < rmax) ? d : -1;
+                epi_apply<DT, EPI, EM>(it, rs, gbase + trow * np, dpos, af, in[R & 1][g]);
+              }
+            });
           });
+        };
+        if constexpr (EPI == EPI_POLYP || EPI == EPI_POLYX) {
+          body(std::integral_constant<int, 0>());
+        } else {
+          if (it.flags & F_E_NONE) body(std::integral_constant<int, 0>());
+          else if (it.flags & F_E_F64) body(std::integral_constant<int, 1>());
+          else body(std::integral_constant<int, 2>());
         }
       }
     }
