@@ -142,6 +142,17 @@ __device__ __forceinline__ double from_op<_Float16>(_Float16 v) { return (double
 // wait counter, coupling the LDS pipeline to outstanding global loads.
 template <class T> using gptr = const __attribute__((address_space(1))) T*;
 template <class T> using gptr_mut = __attribute__((address_space(1))) T*;
+// LDS DMA of one 16-byte chunk per lane to LDS address lds (wave-uniform,
+// through M0) + 16 * lane, written as assembly so that the compiler does not
+// count it as an LDS write: it would otherwise wait for every DMA in flight
+// (vmcnt(0)) before each transposing LDS read, because it cannot tell which
+// LDS those reads touch.  The K loop waits for its DMAs itself (vmcnt +
+// barrier).  The s_nop gives the M0 write the wait state an LDS DMA needs.
+__device__ __forceinline__ void lds_dma16(__amdgpu_buffer_rsrc_t r, unsigned lds, int voff) {
+  asm volatile("s_nop 0\n\tbuffer_load_dwordx4 %0, %1, 0 offen lds" ::"v"(voff), "s"(r),
+               "{m0}"(__builtin_amdgcn_readfirstlane(lds))
+               : "memory");
+}
 template <class T>
 __device__ __forceinline__ T gld(const void* p, int64_t i) { return ((gptr<T>)p)[i]; }
 template <class T>
@@ -693,11 +704,8 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
     else
       __syncthreads();
   };
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = threadIdx.x >> 6;  // wave-uniform
   const int wr = wave / NWC, wc = wave % NWC;
-  const int lr = lane % MI, lq = lane / MI;
 
   // tile range of this workgroup
   int t_begin, t_end, t_step;
@@ -718,6 +726,14 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
 
   const int tbase = tile_start[0];
   for (int t = t_begin; t < t_end; t += t_step) {
+    // The per-thread indices are re-derived for every tile from an opaque
+    // copy of the thread index: the addresses built from them are then
+    // computed per tile and dead during the epilogue, instead of being
+    // hoisted to the kernel's start and spilled.
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63;
+    const int lr = lane % MI, lq = lane / MI;
     // locate the item (binary search over prefix sums)
     const int tv = t + tbase;
     int lo = 0, hi = nitems - 1;
@@ -777,14 +793,21 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
           const_cast<T*>(Bs_g), (short)0, ((BK - 1) * np + BN) * (int)sizeof(T), 0x00020000);
       if constexpr (ADMA) {
         // position p = NT*u + tid of LDS buffer dbuf (wave-uniform base, lane
-        // offset 16 bytes per lane) receives chunk (p % CPR) ^ aswz(row)
+        // offset 16 bytes per lane) receives chunk (p % CPR) ^ aswz(row).
+        // The ring issues its DMAs as assembly (it waits for them itself);
+        // the other tiles rely on the compiler's wait at __syncthreads.
 #pragma unroll
         for (int u = 0; u < A_PER_T; ++u) {
           const int p = tid + NT * u;
           const int r = p / CPR, cc = (p % CPR) ^ aswz(r);
-          __attribute__((address_space(3))) void* dst =
-              (__attribute__((address_space(3))) void*)(&As[dbuf][(NT * u + wave * 64) * W]);
-          __builtin_amdgcn_raw_ptr_buffer_load_lds(ra_rs, dst, 16, (r * np + cc * W) * (int)sizeof(T), 0, 0, 0);
+          if constexpr (RING) {
+            lds_dma16(ra_rs, (unsigned)(size_t)(__attribute__((address_space(3))) void*)(&As[dbuf][(NT * u + wave * 64) * W]),
+                      (r * np + cc * W) * (int)sizeof(T));
+          } else {
+            __attribute__((address_space(3))) void* dst =
+                (__attribute__((address_space(3))) void*)(&As[dbuf][(NT * u + wave * 64) * W]);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ra_rs, dst, 16, (r * np + cc * W) * (int)sizeof(T), 0, 0, 0);
+          }
         }
       } else {
 #pragma unroll
@@ -800,9 +823,8 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
         for (int u = 0; u < BR_PER_T; ++u) {
           const int p = tid + NT * u;
           const int r = p / (BN / W), cc = (p % (BN / W)) ^ bsw(r);
-          __attribute__((address_space(3))) void* dst =
-              (__attribute__((address_space(3))) void*)(&Bs[dbuf][(NT * u + wave * 64) * W]);
-          __builtin_amdgcn_raw_ptr_buffer_load_lds(rb_rs, dst, 16, (r * np + cc * W) * (int)sizeof(T), 0, 0, 0);
+          lds_dma16(rb_rs, (unsigned)(size_t)(__attribute__((address_space(3))) void*)(&Bs[dbuf][(NT * u + wave * 64) * W]),
+                    (r * np + cc * W) * (int)sizeof(T));
         }
       } else {
 #pragma unroll
@@ -873,33 +895,22 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
         // lane (g, jj, a) = (lane / 16, lane / 4 % 4, lane % 4) supplies row
         // r (then r + 4), columns c .. c+3; lane l receives k-rows
         // ch*KC + 8 (l / 32) + 0..7 of column wc*WN + j*MI + l % 32.  The
-        // reads are written as assembly that waits for them in the same
-        // block: through the builtin the compiler would first wait for every
-        // LDS DMA in flight, which would drain the ring at every step.
-        static_assert(RN == 2, "the transposing reads are written for two B fragments");
+        // ring's DMAs are assembly (lds_dma16), so the compiler adds no wait
+        // for them before these reads, and waits for the reads themselves
+        // only where the MFMAs use them.
         typedef short s4v __attribute__((ext_vector_type(4)));
         typedef short s8v __attribute__((ext_vector_type(8)));
+        typedef __attribute__((address_space(3))) s4v* lp;
         const int g = lane >> 4, jj = (lane >> 2) & 3, a = lane & 3;
         const int r = ch * KC + 8 * (g >> 1) + jj;
-        unsigned ad[RN];
 #pragma unroll
         for (int j = 0; j < RN; ++j) {
           const int c = wc * WN + j * MI + 16 * (g & 1) + 4 * a;
-          ad[j] = (unsigned)(size_t)(__attribute__((address_space(3))) const T*)(
-              &Bs[buf][r * BN + ((c / W) ^ bsw(r)) * W + (c % W)]);
+          const lp p = (lp)(__attribute__((address_space(3))) T*)(&Bs[buf][r * BN + ((c / W) ^ bsw(r)) * W + (c % W)]);
+          const s4v lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16(p);
+          const s4v hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16(p + BN);
+          fb[j] = __builtin_bit_cast(FV, (s8v)__builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
         }
-        s4v lo0, hi0, lo1, hi1;
-        asm volatile(
-            "ds_read_b64_tr_b16 %0, %4\n\t"
-            "ds_read_b64_tr_b16 %1, %4 offset:%6\n\t"
-            "ds_read_b64_tr_b16 %2, %5\n\t"
-            "ds_read_b64_tr_b16 %3, %5 offset:%6\n\t"
-            "s_waitcnt lgkmcnt(0)"
-            : "=&v"(lo0), "=&v"(hi0), "=&v"(lo1), "=&v"(hi1)
-            : "v"(ad[0]), "v"(ad[1]), "n"(4 * BN * (int)sizeof(T))
-            : "memory");
-        fb[0] = __builtin_bit_cast(FV, (s8v)__builtin_shufflevector(lo0, hi0, 0, 1, 2, 3, 4, 5, 6, 7));
-        fb[1] = __builtin_bit_cast(FV, (s8v)__builtin_shufflevector(lo1, hi1, 0, 1, 2, 3, 4, 5, 6, 7));
       } else {
 #pragma unroll
         for (int j = 0; j < RN; ++j)
@@ -961,10 +972,24 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
     // the barrier then publishes tile kt+1 to all waves and frees stage
     // kt % NS, which is refilled with tile kt+NS at once.  Every thread
     // issues LPT loads per tile in every K tile (clamped tile index after
-    // the last), so the outstanding count is the same everywhere.
+    // the last), so the outstanding count is the same everywhere.  Every
+    // step interleaves its MFMAs with the next step's fragment reads (one
+    // LDS read after each MFMA), so the reads of all waves are spread over
+    // the step instead of arriving in bursts; at the barrier step they
+    // start right after the barrier.  FP16 fine step at n = 4096: 668 TFLOP/s
+    // with the reads issued as a block after the MFMAs (the transposing
+    // ones waited for inside their own assembly block), 700 interleaved.
     constexpr int LPT = A_PER_T + BR_PER_T;
     auto ring_sync = [](auto n_c) {
       asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(decltype(n_c)::value) : "memory");
+    };
+    // scheduling pattern of a step: MFMA, LDS read, MFMA, ... (RM + 2 RN
+    // reads, RM RN MFMAs)
+    auto interleave = [&]() {
+      static_for(std::make_integer_sequence<int, RM * RN>(), [&](auto) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      });
     };
     auto ktile_ring = [&](int kt) {
       const int cur = kt & (NS - 1), nxt = (kt + 1) & (NS - 1);
@@ -974,16 +999,17 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
         FV(&fb_c)[RN] = (sidx & 1) ? fb1 : fb0;
         FV(&fa_n)[RM] = (sidx & 1) ? fa0 : fa1;
         FV(&fb_n)[RN] = (sidx & 1) ? fb0 : fb1;
-        // the MFMAs go first: the fragment reads of the next step wait for
-        // their data, which the other wave of the SIMD covers
-        __builtin_amdgcn_sched_barrier(0);
-        mfma_step(fa_c, fb_c);
-        __builtin_amdgcn_sched_barrier(0);
         if constexpr (sidx + 1 < NSTEP) {
           read_frag(fa_n, fb_n, cur, sidx + 1);
+          mfma_step(fa_c, fb_c);
+          interleave();
         } else {
           ring_sync(std::integral_constant<int, (NS - 2) * LPT>());
+          __builtin_amdgcn_sched_barrier(0);
           read_frag(fa_n, fb_n, nxt, 0);
+          mfma_step(fa_c, fb_c);
+          interleave();
+          __builtin_amdgcn_sched_barrier(0);
           gload(min(kt + NS, nk - 1), 0, cur);
         }
         __builtin_amdgcn_sched_barrier(0);

@@ -192,13 +192,44 @@ def learned_vs_euler(kind=fm.FM_FLOW_INV_HOMOTOPY, dtype=None, tol=None, options
     return res
 
 
+def vendor_gemm():
+    """Reference for the 16-bit products: torch.matmul (the vendor BLAS) on 16
+    seeded random n x n products per call, FP16 and BF16 at n = 4096 and FP16
+    at n = 8192; the rate such random data sustains on this chip (its clock
+    drops under the matrix units' load) bounds what the fine-step products
+    can reach."""
+    out = []
+    for name, dt, n in (("f16", torch.float16, 4096), ("bf16", torch.bfloat16, 4096), ("f16", torch.float16, 8192)):
+        batch = 16 if n == 4096 else 4
+        g = torch.Generator(device="cuda").manual_seed(7)
+        a = torch.randn(batch, n, n, device="cuda", dtype=torch.float32, generator=g).to(dt)
+        b = torch.randn(batch, n, n, device="cuda", dtype=torch.float32, generator=g).to(dt)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            torch.matmul(a, b, out=c)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            torch.matmul(a, b, out=c)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out.append({"workload": "torch_matmul_%s_%dx%d" % (name, batch, n), "ms_per_call": ms,
+                    "tflops": 2.0 * batch * n ** 3 / (ms * 1e-3) / 1e12})
+        del a, b, c
+    return out
+
+
 ROWS = {"example1": example1, "example2_cn": example2_cn, "exp": exp_variants, "aima": aima, "cos": cosine, "batched": batched,
         "batched_tol1e-2": lambda: batched(tol=1e-2),
         "learned": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY),
         "learned_f32": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY, "f32", 1e-6),
         "learned_f32_coarse64": lambda: learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY, "f32", 1e-7, "coarse_f64=1"),
         "learned_steady": lambda: learned_vs_euler(fm.FM_FLOW_INV_STEADY),
-        "learned_steady_coarse64": lambda: learned_vs_euler(fm.FM_FLOW_INV_STEADY, options="coarse_f64=1")}
+        "learned_steady_coarse64": lambda: learned_vs_euler(fm.FM_FLOW_INV_STEADY, options="coarse_f64=1"),
+        "vendor_gemm": vendor_gemm}
 
 
 def main():

@@ -34,8 +34,10 @@ def _solve(kind, A, dtype, prm, options=None):
     flow = fm.fm_flow_create([(kind, dev(A))], dtype, options)
     try:
         out = empty(n)
+        t0 = time.time()
         st, stats = fm.fm_parareal_solve(flow, None, [out], [prm])
         torch.cuda.synchronize()
+        say("  %s solve: status %d, %d iterations, %.1f s" % (dtype, st, stats[0]["iters"], time.time() - t0))
         return st, stats[0], out
     finally:
         fm.fm_destroy(flow)
