@@ -21,8 +21,17 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+# pytest's capture manager (set by conftest): progress lines of the long
+# tests bypass output capture, so a run shows which step it is in.
+_capman = None
+
+
 def say(msg):
-    print(msg, flush=True)
+    if _capman is not None:
+        with _capman.global_and_fixture_disabled():
+            print(msg, flush=True)
+    else:
+        print(msg, flush=True)
 
 
 def increments_agree(gpu, ref, rtol=1e-6, atol=1e-14):

@@ -34,6 +34,7 @@ def _solve(kind, A, dtype, prm, options=None):
     flow = fm.fm_flow_create([(kind, dev(A))], dtype, options)
     try:
         out = empty(n)
+        say("  %s solve of order %d started" % (dtype, n))
         t0 = time.time()
         st, stats = fm.fm_parareal_solve(flow, None, [out], [prm])
         torch.cuda.synchronize()
