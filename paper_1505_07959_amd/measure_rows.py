@@ -193,32 +193,57 @@ def learned_vs_euler(kind=fm.FM_FLOW_INV_HOMOTOPY, dtype=None, tol=None, options
 
 
 def vendor_gemm():
-    """Reference for the 16-bit products: torch.matmul (the vendor BLAS) on 16
-    seeded random n x n products per call, FP16 and BF16 at n = 4096 and FP16
-    at n = 8192; the rate such random data sustains on this chip (its clock
-    drops under the matrix units' load) bounds what the fine-step products
-    can reach."""
+    """Reference for the products: torch.matmul (the vendor BLAS) on seeded
+    random n x n products -- FP16 and BF16 at n = 4096 (16 per call), FP16 at
+    n = 8192 (4 per call), FP64 at n = 4096 (4 per call) -- and, for the
+    RK4-epilogue product, the same FP16 products followed by the stage
+    update as separate elementwise operations (k = -P, accumulator += 2 k,
+    next operand = x + h/2 k in FP16, FP32 state), the unfused equivalent of
+    one stage-2 launch.  The rate random data sustains on this chip (its
+    clock drops under the matrix units' load) bounds what the fine-step
+    products can reach."""
     out = []
-    for name, dt, n in (("f16", torch.float16, 4096), ("bf16", torch.bfloat16, 4096), ("f16", torch.float16, 8192)):
-        batch = 16 if n == 4096 else 4
+
+    def timed(fn, reps=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for name, dt, n, batch in (("f16", torch.float16, 4096, 16), ("bf16", torch.bfloat16, 4096, 16),
+                               ("f16", torch.float16, 8192, 4), ("f64", torch.float64, 4096, 4)):
         g = torch.Generator(device="cuda").manual_seed(7)
         a = torch.randn(batch, n, n, device="cuda", dtype=torch.float32, generator=g).to(dt)
         b = torch.randn(batch, n, n, device="cuda", dtype=torch.float32, generator=g).to(dt)
         c = torch.empty_like(a)
-        for _ in range(3):
-            torch.matmul(a, b, out=c)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 20
-        e0.record()
-        for _ in range(reps):
-            torch.matmul(a, b, out=c)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        ms = timed(lambda: torch.matmul(a, b, out=c))
         out.append({"workload": "torch_matmul_%s_%dx%d" % (name, batch, n), "ms_per_call": ms,
                     "tflops": 2.0 * batch * n ** 3 / (ms * 1e-3) / 1e12})
+        if name == "f16" and n == 4096:
+            x = torch.randn(batch, n, n, device="cuda", dtype=torch.float32, generator=g)
+            kq = torch.randn(batch, n, n, device="cuda", dtype=torch.float32, generator=g)
+            y = torch.empty_like(a)
+            h = 1e-3
+
+            def stage():
+                torch.matmul(a, b, out=c)
+                k = -c.float()
+                kq.add_(k, alpha=2.0)
+                torch.add(x, k, alpha=0.5 * h, out=k)
+                y.copy_(k)
+
+            ms = timed(stage)
+            out.append({"workload": "torch_matmul_f16_%dx%d_then_rk4_stage_update" % (batch, n), "ms_per_call": ms,
+                        "tflops": 2.0 * batch * n ** 3 / (ms * 1e-3) / 1e12})
+            del x, kq, y
         del a, b, c
+        torch.cuda.empty_cache()
     return out
 
 
