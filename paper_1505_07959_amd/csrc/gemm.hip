@@ -917,6 +917,13 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
           fb[j] = *(const FV*)(&Bs[buf][((ch * NQ + lq) * BN + bswz(wc * WN + j * MI + lr)) * V + sub * SUBV]);
       }
     };
+    // FP64: the MFMAs of k-value t of a step (t < SUBV)
+    auto mfma_k = [&](const FV (&fa)[RM], const FV (&fb)[RN], int t) {
+#pragma unroll
+      for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j) mma1<DT>(acc[i][j], fa[i][t], fb[j][t]);
+    };
     auto mfma_step = [&](const FV (&fa)[RM], const FV (&fb)[RN]) {
       if constexpr (DT == DT_F64 || DT == DT_F32) {
         // k-value outermost: consecutive MFMAs update different accumulators
@@ -952,17 +959,47 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
         FV(&fb_c)[RN] = (sidx & 1) ? fb1 : fb0;
         FV(&fa_n)[RM] = (sidx & 1) ? fa0 : fa1;
         FV(&fb_n)[RN] = (sidx & 1) ? fb0 : fb1;
-        if constexpr (sidx + 1 < NSTEP) {
-          read_frag(fa_n, fb_n, cur, sidx + 1);
-        } else {
+        if constexpr (DT == DT_F64 && sidx + 1 == NSTEP) {
+          // FP64: the per-tile work runs in the MFMAs' shadow.  The MFMAs
+          // of the step's first k-value carry the LDS stores of the next
+          // tile (one store and two VALU instructions after each), those
+          // of the second k-value the fragment reads and global loads
+          // issued after the barrier; the per-accumulator order of the
+          // MFMAs is that of mfma_step.  FP64 fine step at n = 4096:
+          // 65.9 -> 69.5 TFLOP/s (the same for FP32 lost 1.6 %).
+          static_assert(SUBV == 2, "the FP64 step is split by k-value");
+          __builtin_amdgcn_sched_barrier(0);
+          mfma_k(fa_c, fb_c, 0);
           lstore(cur ^ 1, set);
+          static_for(std::make_integer_sequence<int, RM * RN>(), [&](auto) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // LDS write
+            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // VALU
+          });
+          __builtin_amdgcn_sched_barrier(0);
           __syncthreads();
           read_frag(fa_n, fb_n, cur ^ 1, 0);
-          gload(min(kt + 1 + PF, nk - 1), set, cur);  // A (ADMA): into the buffer just released
+          gload(min(kt + 1 + PF, nk - 1), set, cur);
+          mfma_k(fa_c, fb_c, 1);
+          static_for(std::make_integer_sequence<int, RM * RN>(), [&](auto) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // global load
+          });
+          __builtin_amdgcn_sched_barrier(0);
+        } else {
+          if constexpr (sidx + 1 < NSTEP) {
+            read_frag(fa_n, fb_n, cur, sidx + 1);
+          } else {
+            lstore(cur ^ 1, set);
+            __syncthreads();
+            read_frag(fa_n, fb_n, cur ^ 1, 0);
+            gload(min(kt + 1 + PF, nk - 1), set, cur);  // A (ADMA): into the buffer just released
+          }
+          __builtin_amdgcn_sched_barrier(0);
+          mfma_step(fa_c, fb_c);
+          __builtin_amdgcn_sched_barrier(0);
         }
-        __builtin_amdgcn_sched_barrier(0);
-        mfma_step(fa_c, fb_c);
-        __builtin_amdgcn_sched_barrier(0);
       });
     };
 
