@@ -601,7 +601,9 @@ constexpr int gemm_nt() {
   return (BM == 256 && DT != DT_F64 && DT != DT_F32) ? 512 : 256;
 }
 
-template <int DT, int BM, int BK, int EPI>
+// ILV (FP64 only): the interleaved schedule of a K tile's last step, for
+// launches of large products (see ktile)
+template <int DT, int BM, int BK, int EPI, bool ILV = false>
 __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 || BK == 16)) ? 2 : 1) void gemm_kernel(const GItem* __restrict__ items,
                                                    const int* __restrict__ tile_start, int nitems,
                                                    int total_tiles, const int* __restrict__ live) {
@@ -959,8 +961,11 @@ __global__ __launch_bounds__((gemm_nt<DT, BM>()), (BM == 128 && (DT != DT_F64 ||
         FV(&fb_c)[RN] = (sidx & 1) ? fb1 : fb0;
         FV(&fa_n)[RM] = (sidx & 1) ? fa0 : fa1;
         FV(&fb_n)[RN] = (sidx & 1) ? fb0 : fb1;
-        if constexpr (DT == DT_F64 && sidx + 1 == NSTEP) {
-          // FP64: the per-tile work runs in the MFMAs' shadow.  The MFMAs
+        if constexpr (DT == DT_F64 && ILV && sidx + 1 == NSTEP) {
+          // FP64, launches of large products (ILV; on launches of many small
+          // products this schedule more than doubled the time of their
+          // latency-bound launches, which keep the block order): the
+          // per-tile work runs in the MFMAs' shadow.  The MFMAs
           // of the step's first k-value carry the LDS stores of the next
           // tile (one store and two VALU instructions after each), those
           // of the second k-value the fragment reads and global loads
@@ -1197,14 +1202,25 @@ template <int DT, int BM, int BK>
 hipError_t launch_cfg(int epi, const GItem* items, const int* ts, int nitems, int total, int grid,
                       const int* live, hipStream_t st) {
   dim3 g(grid), b(gemm_nt<DT, BM>());
-  switch (epi) {
-    case EPI_AFFINE: hipLaunchKernelGGL((gemm_kernel<DT, BM, BK, EPI_AFFINE>), g, b, 0, st, items, ts, nitems, total, live); break;
-    case EPI_RK4: hipLaunchKernelGGL((gemm_kernel<DT, BM, BK, EPI_RK4>), g, b, 0, st, items, ts, nitems, total, live); break;
-    case EPI_EULER: hipLaunchKernelGGL((gemm_kernel<DT, BM, BK, EPI_EULER>), g, b, 0, st, items, ts, nitems, total, live); break;
-    case EPI_POLYP: hipLaunchKernelGGL((gemm_kernel<DT, BM, BK, EPI_POLYP>), g, b, 0, st, items, ts, nitems, total, live); break;
-    case EPI_POLYX: hipLaunchKernelGGL((gemm_kernel<DT, BM, BK, EPI_POLYX>), g, b, 0, st, items, ts, nitems, total, live); break;
-    default: return hipErrorInvalidValue;
-  }
+  // FP64: the interleaved schedule when the items average at least 64 tiles
+  // of 128 (orders of 1024 and more)
+  const bool ilv = DT == DT_F64 && BM == 128 && total >= 64 * nitems;
+  auto go = [&](auto ilv_c) -> hipError_t {
+    constexpr bool I = decltype(ilv_c)::value;
+    switch (epi) {
+      case EPI_AFFINE: hipLaunchKernelGGL((gemm_kernel<DT, BM, BK, EPI_AFFINE, I>), g, b, 0, st, items, ts, nitems, total, live); break;
+      case EPI_RK4: hipLaunchKernelGGL((gemm_kernel<DT, BM, BK, EPI_RK4, I>), g, b, 0, st, items, ts, nitems, total, live); break;
+      case EPI_EULER: hipLaunchKernelGGL((gemm_kernel<DT, BM, BK, EPI_EULER, I>), g, b, 0, st, items, ts, nitems, total, live); break;
+      case EPI_POLYP: hipLaunchKernelGGL((gemm_kernel<DT, BM, BK, EPI_POLYP, I>), g, b, 0, st, items, ts, nitems, total, live); break;
+      case EPI_POLYX: hipLaunchKernelGGL((gemm_kernel<DT, BM, BK, EPI_POLYX, I>), g, b, 0, st, items, ts, nitems, total, live); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+  };
+  hipError_t e;
+  if constexpr (DT == DT_F64 && BM == 128) e = ilv ? go(std::true_type()) : go(std::false_type());
+  else e = go(std::false_type());
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
