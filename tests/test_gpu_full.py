@@ -301,6 +301,47 @@ def test_learned_beats_euler_to_1e8():
     assert el <= 1e-8 and ee <= 1e-8
 
 
+
+def test_learned_beats_euler_fp32_products():
+    """The same gain with the FP32 products of the learned-coarse workload
+    (n = 2048, N = 128, S = 8) and the coarse step's products in FP64
+    (option coarse_f64=1; with FP32 coarse products the learned step stalls
+    at its FP32 floor near 7e-6), to increment 1e-7: the trained network
+    takes fewer iterations and less wall time than Euler, with no restart,
+    and both reach the FP32 fine solution (the serial fine solve, same
+    kernels) to 1e-6."""
+    from paper_1505_07959_amd import fm
+    n, N, S, tol = 2048, 128, 8, 1e-7
+    A, Q, lam = inputs.learned_eval_problem(n)
+    path = os.path.join(MODELS, "homotopy_n256.fmw")
+    flow = fm.fm_flow_create([(HOMOTOPY, dev(A))], "f32", "coarse_f64=1;coarse_model=" + path)
+    res = {}
+    try:
+        out = empty(n)
+        prm = {"T": 1.0, "N": N, "fine_steps": S, "max_iter": N, "tol": tol}
+        say("learned vs Euler, FP32 products, FP64 coarse products, to %g" % tol)
+        fm.fm_parareal_solve(flow, None, [out], [dict(prm, max_iter=1, coarse=fm.FM_COARSE_LEARNED)])  # warm-up
+        for name, coarse in (("euler", fm.FM_COARSE_EULER), ("learned", fm.FM_COARSE_LEARNED)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, stats = fm.fm_parareal_solve(flow, None, [out], [dict(prm, coarse=coarse)])
+            torch.cuda.synchronize()
+            res[name] = (st, stats[0], time.perf_counter() - t0, host(out))
+        X0 = [torch.eye(n, dtype=torch.float64, device="cuda")]
+        Xs = [empty(n)]
+        fm.fm_fine_propagate(flow, 1.0, 0.0, N * S, X0, Xs)
+        ser = host(Xs[0])
+    finally:
+        fm.fm_destroy(flow)
+    el, ee = rel(res["learned"][3], ser), rel(res["euler"][3], ser)
+    say("  iterations %d vs %d, %.2f s vs %.2f s, error vs serial fine %.1e vs %.1e" % (
+        res["learned"][1]["iters"], res["euler"][1]["iters"], res["learned"][2], res["euler"][2], el, ee))
+    assert res["learned"][0] == fm.FM_OK and res["euler"][0] == fm.FM_OK
+    assert res["learned"][1]["learned_restarts"] == 0
+    assert res["learned"][1]["iters"] < res["euler"][1]["iters"]
+    assert res["learned"][2] < res["euler"][2]
+    assert el <= 1e-6 and ee <= 1e-6
+
 def test_maximum_order_fp64():
     """The largest order the interface accepts, with a ragged tail: n = 16383
     (padded to 16384), homotopy flow, FP64, N = 2 slices of 2 RK4 steps, one
