@@ -24,6 +24,13 @@ launches (affine and RK4-epilogue products of every RK4 step), timed with
 HIP events on the solve's stream around each hipGraph replay of one RK4
 step; achieved = algorithmic flops (2 n^3 per slice product) / time.
 
+learned_vs_euler (default workload only, after the timed region and the
+CPU baseline, if it ends within --learned-budget-s of the process start):
+the learned coarse step against forward Euler on the n = 2048 homotopy
+(N = 128 slices, 8 RK4 steps per slice, FP64, to increment 1e-8), each
+solve timed after one warm-up solve of the flow, with the iteration counts,
+the wall times and each result's distance from the serial fine solution.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 
@@ -114,6 +121,15 @@ def plan_next_solve(now, solve_s, steps_done, steps_target, budget_s, reserve_s)
     return now + solve_s + reserve_s <= budget_s
 
 
+LEARNED_LEG_S = 75.0  # the learned-vs-Euler leg's wall time, with margin (about 55 s measured)
+
+
+def plan_learned_leg(now, budget_s, est_s=LEARNED_LEG_S):
+    """Whether the learned-vs-Euler leg, started `now` seconds after the
+    process start, is expected to end within `budget_s`."""
+    return now + est_s <= budget_s
+
+
 def solve_work(n, N, S, iters):
     """Fine RK4 steps and coarse Euler steps of a solve of `iters` iterations:
     iteration k re-solves the slices n >= k; the sweep of iteration k takes a
@@ -141,6 +157,9 @@ def main():
     ap.add_argument("--max-iter", type=int, default=64)
     ap.add_argument("--cpu-sample-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-Euler leg")
+    ap.add_argument("--learned-budget-s", type=float, default=540.0,
+                    help="wall-clock limit from process start for the learned-vs-Euler leg")
     ap.add_argument("--serial", action="store_true",
                     help="also time the serial fine solve after the benchmark (off by default: its one-product "
                          "launches of the same kernel would blend into a profile's per-kernel average)")
@@ -245,6 +264,35 @@ def main():
         log("cpu baseline (%d oracle RK4 steps at n=%d)" % (args.cpu_sample_steps, n))
         cpu = cpu_baseline(A, n, fine_steps_total, coarse_steps_total, args.cpu_sample_steps)
 
+    # outside the timed region: learned vs Euler coarse step (the default
+    # workload only, so that runs of other shapes keep their launches alone)
+    learned = None
+    default_run = (args.dtype, n, N, S, args.coarse, args.tol, args.max_iter, args.tile, args.coarse_f64) == \
+        ("f64", 4096, 64, 16, "euler", 1e-8, 64, None, False)
+    if default_run and not args.no_learned:
+        now = time.time() - T_PROCESS
+        if plan_learned_leg(now, args.learned_budget_s):
+            from paper_1505_07959_amd import measure_rows
+            log("learned vs Euler coarse step: n=2048 homotopy, N=128, S=8, FP64, to 1e-8")
+            rows = measure_rows.learned_vs_euler(fm.FM_FLOW_INV_HOMOTOPY)
+            by = {("learned" if r["workload"].endswith("_learned") else "euler"): r for r in rows}
+            learned = {"workload": "inverse homotopy n=2048 SPD lam~loguniform[1e-2,10] seed 4, N=128 slices, RK4 8 "
+                                   "steps/slice, FP64 products, stop at increment <= 1e-08; network "
+                                   "models/homotopy_n256.fmw (trained at n=256)",
+                       "serial_fine_seconds": by["euler"]["serial_fine_seconds"]}
+            for k in ("euler", "learned"):
+                r = by[k]
+                learned[k] = {"iterations": r["iterations"], "seconds": r["seconds"], "status": r["status"],
+                              "restarts": r["restarts"], "rel_diff_vs_serial_fine": r["rel_diff_vs_serial_fine"]}
+            learned["learned_fewer_iterations_and_faster"] = (
+                learned["learned"]["iterations"] < learned["euler"]["iterations"]
+                and learned["learned"]["seconds"] < learned["euler"]["seconds"])
+            log("learned %d iterations %.1f s, Euler %d iterations %.1f s" %
+                (learned["learned"]["iterations"], learned["learned"]["seconds"],
+                 learned["euler"]["iterations"], learned["euler"]["seconds"]))
+        else:
+            log("learned-vs-Euler leg skipped: it would end past %.0f s" % args.learned_budget_s)
+
     key = "gemm_%s_fine_step_n%d" % (args.dtype, n)
     res = {
         "metric": METRIC,
@@ -280,6 +328,7 @@ def main():
                                % (launches, avg_launch_ms, flops_per_launch)},
         "cpu_baseline": cpu,
         "serial_fine": serial,
+        "learned_vs_euler": learned,
     }
     print(json.dumps(res), flush=True)
 

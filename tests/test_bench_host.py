@@ -68,3 +68,12 @@ def test_solve_work_counts_live_slices():
     fine, coarse = bench.solve_work(4096, 4, 2, 3)
     assert fine == (4 + 3 + 2) * 2
     assert coarse == 4 + (3 + 2 + 1)
+
+
+def test_learned_leg_runs_only_if_it_ends_within_its_limit():
+    # the benchmark's usual end of the CPU baseline (~370 s): the leg fits the
+    # 540 s limit; a run whose timed region used its whole 450 s budget
+    # (plus the baseline) does not start it, so the command stays under 600 s
+    assert bench.plan_learned_leg(now=370.0, budget_s=540.0)
+    assert not bench.plan_learned_leg(now=480.0, budget_s=540.0)
+    assert bench.LEARNED_LEG_S + 450.0 + 30.0 > 540.0
