@@ -178,7 +178,8 @@ def main():
     ap.add_argument("--fine-steps", type=int, default=16)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=64)
-    ap.add_argument("--cpu-sample-steps", type=int, default=8)
+    ap.add_argument("--cpu-sample-steps", type=int, default=12,
+                    help="oracle RK4 steps timed for the CPU baseline (about 10-13 s of CPU work at n=4096)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-Euler leg")
     ap.add_argument("--learned-budget-s", type=float, default=540.0,
