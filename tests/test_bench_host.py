@@ -8,6 +8,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 import bench
 
@@ -77,3 +78,27 @@ def test_learned_leg_runs_only_if_it_ends_within_its_limit():
     assert bench.plan_learned_leg(now=370.0, budget_s=540.0)
     assert not bench.plan_learned_leg(now=480.0, budget_s=540.0)
     assert bench.LEARNED_LEG_S + 450.0 + 30.0 > 540.0
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                                    "paper_1505_07959_amd", "libfm.so")),
+                    reason="library not built")
+def test_learned_leg_reports_both_coarse_steps(monkeypatch):
+    """The leg's summary carries each coarse step's iterations, time, status,
+    restarts and distance from the serial fine solution, and says whether
+    the learned step took fewer iterations and less time."""
+    from paper_1505_07959_amd import fm, measure_rows
+
+    def rows(it_e, s_e, it_l, s_l):
+        base = {"status": 0, "restarts": 0, "rel_diff_vs_serial_fine": 1e-11, "serial_fine_seconds": 2.0}
+        return [dict(base, workload="homotopy_n2048_N128_S8_f64_tol1e-08_euler", iterations=it_e, seconds=s_e),
+                dict(base, workload="homotopy_n2048_N128_S8_f64_tol1e-08_learned", iterations=it_l, seconds=s_l)]
+
+    monkeypatch.setattr(measure_rows, "learned_vs_euler", lambda kind: rows(11, 22.8, 7, 16.5))
+    r = bench.learned_leg(fm)
+    assert r["euler"]["iterations"] == 11 and r["learned"]["iterations"] == 7
+    assert r["learned"]["seconds"] == 16.5 and r["serial_fine_seconds"] == 2.0
+    assert r["learned_fewer_iterations_and_faster"]
+    # fewer iterations but slower is not a win
+    monkeypatch.setattr(measure_rows, "learned_vs_euler", lambda kind: rows(11, 22.8, 7, 30.0))
+    assert not bench.learned_leg(fm)["learned_fewer_iterations_and_faster"]
